@@ -1,0 +1,198 @@
+"""Benchmark: streaming Tucker updates per second on one MI355X.
+
+Workload: the advecting-blob stream with 128 x 128 x 128 spatial slices and 16
+variables (4-way slices, d = 5), 400 slices, tau = 1e-4, initial ST-HOSVD on
+the first 20 slices. A step is one streaming update (Alg. 5) of one slice. All
+slices are generated on the GPU and resident in HBM before the timed region;
+the timed region covers exactly --steps updates after --warmup updates.
+
+Prints one JSON line with the throughput, a roofline entry for the kernel group
+that takes the most device time (from HIP events recorded by the library on its
+own stream), and the FP64 CPU oracle timed on a bounded sample of the same
+stream on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "slices/s at eps-bounded error: bf16x3 MFMA vs FP32 path; TTM/Gram % roofline"
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0 / 3.0, "fp64": 78.6}
+
+WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_init=20,
+                tau=1e-4, seed=1001)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def roofline(prof, precision):
+    """Roofline entry of the group with the most device time."""
+    group = max(prof, key=lambda g: prof[g]["ms"])
+    p = prof[group]
+    if p["ms"] <= 0 or p["launches"] == 0:
+        return group, None
+    sec = p["ms"] / 1e3
+    ai = p["flops"] / p["bytes"] if p["bytes"] else float("inf")
+    prec_key = "fp64" if group in ("eig", "svd", "ud") else (
+        precision if group in ("ttm1", "ttm", "ttm_ext", "gram") else "fp32")
+    peak_f = PEAK_TFLOPS[prec_key]
+    ridge = peak_f * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if ai >= ridge:
+        achieved = p["flops"] / sec / 1e12
+        entry = dict(bound="mfma", achieved=round(achieved, 3), peak=peak_f, unit="TFLOP/s",
+                     frac=round(achieved / peak_f, 4))
+    else:
+        achieved = p["bytes"] / sec / 1e9
+        entry = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                     frac=round(achieved / PEAK_HBM_GBS, 4))
+    entry.update(kernel=group, launches=p["launches"], avg_ms=round(p["ms"] / p["launches"], 5),
+                 flops_per_launch=p["flops"] / p["launches"],
+                 bytes_per_launch=p["bytes"] / p["launches"], traffic=None)
+    return group, entry
+
+
+def cpu_baseline(host_slices, n_init, tau, n_updates):
+    """The FP64 oracle on the host: init on the first slices (untimed), then
+    `n_updates` timed updates of the same stream."""
+    import numpy as np
+
+    from oracle import StreamingTucker as Oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    x0 = np.stack(host_slices[:n_init], axis=-1)
+    orc = Oracle(x0, tau)
+    del x0
+    t0 = time.perf_counter()
+    for t in range(n_init, n_init + n_updates):
+        orc.update(host_slices[t])
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_updates / dt, 4), unit="slices/s", cores=int(threads),
+                kind="oracle",
+                sample=f"FP64 oracle updates of slices {n_init}..{n_init + n_updates - 1} of the "
+                       f"same stream after its untimed init on slices 0..{n_init - 1}; "
+                       f"{dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=375)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--cpu-updates", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the streaming update is sequential along the "
+              "stream and this build measures one GPU's share (see DESIGN.md on sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2308_16395_amd as pkg
+    from synth import BlobStream
+
+    w = WORKLOAD
+    n_init = w["n_init"]
+    total = n_init + args.warmup + args.steps
+    if total > w["n_slices"]:
+        raise SystemExit(f"warmup + steps exceed the {w['n_slices'] - n_init} updates of the stream")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = BlobStream(w["space"], w["n_vars"], w["n_blobs"], n_slices=w["n_slices"],
+                        seed=w["seed"])
+    ny = math.prod(stream.dims)
+    log(f"generating {total} slices of {ny} elements on {torch.cuda.get_device_name(0)}")
+    data = torch.empty((total, ny), dtype=torch.float32, device=dev)
+    for t in range(total):
+        data[t] = stream.slice_torch(t, dev, torch.float32)
+    torch.cuda.synchronize()
+
+    st = pkg.StreamingTucker(stream.dims, w["tau"], precision=args.precision, profile=True)
+    t0 = time.perf_counter()
+    st.init(data[:n_init].reshape(-1), n_init)
+    init_s = time.perf_counter() - t0
+    log(f"init {init_s:.2f} s, ranks {st.ranks}")
+    for t in range(n_init, n_init + args.warmup):
+        st.update(data[t])
+    st.profile(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(n_init + args.warmup, total):
+        st.update(data[t])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = st.profile()
+    log(f"timed {args.steps} updates in {dt:.3f} s, ranks {st.ranks}")
+
+    value = args.steps / dt
+    group, roof = roofline(prof, args.precision)
+    bound, _ = st.recon_error()
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {
+            "workload": "advecting-blobs 128x128x128 x 16 variables, 400 slices, tau 1e-4, "
+                        "init 20 slices",
+            "slice_dims": list(stream.dims), "n_slices": w["n_slices"], "n_init": n_init,
+            "eps": w["tau"], "precision": args.precision, "seed": w["seed"],
+        },
+        "roofline": roof,
+        "ranks_final": list(st.ranks),
+        "recon_error_bound": bound,
+        "init_s": round(init_s, 3),
+        "kernels": {g: dict(launches=p["launches"], ms=round(p["ms"], 3),
+                            tflops=round(p["flops"] / p["ms"] / 1e9, 3) if p["ms"] else None,
+                            gbs=round(p["bytes"] / p["ms"] / 1e6, 1) if p["ms"] else None)
+                    for g, p in prof.items() if p["launches"]},
+    }
+    if not args.no_accuracy:
+        # true relative error of the model over every slice seen (outside the timed region)
+        err2 = nrm2 = 0.0
+        for t in range(total):
+            rec = st.reconstruct_slice(t)
+            err2 += torch.sum((rec.double() - data[t].double()) ** 2).item()
+            nrm2 += torch.sum(data[t].double() ** 2).item()
+        result["true_rel_error"] = math.sqrt(err2 / nrm2)
+        result["eps_met"] = result["true_rel_error"] <= w["tau"]
+    if not args.no_cpu_baseline:
+        k = args.cpu_updates
+        host = [data[t].cpu().numpy().astype(np.float64).reshape(stream.dims, order="F")
+                for t in range(n_init + k)]
+        log(f"timing the FP64 oracle on {k} updates")
+        result["cpu_baseline"] = cpu_baseline(host, n_init, w["tau"], k)
+    st.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

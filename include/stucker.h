@@ -1,0 +1,204 @@
+/*
+ * stucker.h - C ABI of the streaming Tucker (streaming ST-HOSVD) library for
+ * AMD MI355X (gfx950).
+ *
+ * The library keeps a Tucker decomposition X ~ C x_1 U_1 ... x_d U_d of a
+ * tensor that grows along its last ("streaming") mode d, one (d-1)-way slice
+ * at a time, without storing past slices (paper: De, Li, Kolla, Phipps,
+ * "Efficient Computation of Tucker Decomposition for Streaming Scientific
+ * Data Compression", Sec. 2.4 problem statement, Sec. 3, Alg. 5).
+ *
+ * Conventions for every call:
+ *  - Return value: ST_OK (0) or a negative ST_E* code. No C++ exception crosses
+ *    this boundary. st_last_error() returns a message for the last failure on
+ *    that handle (valid until the next call on the handle).
+ *  - Tensors are column-major with the first index fastest (Sec. 2.1): a slice
+ *    of shape n_1 x ... x n_{d-1} is the flat array Y[i_1 + n_1 (i_2 + n_2 (...))].
+ *    A C-contiguous torch tensor of shape (n_{d-1}, ..., n_1) is the same memory.
+ *  - Slice inputs are float32 device pointers on the handle's device; the
+ *    caller keeps ownership and the library does not retain them.
+ *  - Calls are synchronous with respect to the host: when a call returns, its
+ *    device work on the handle's stream has finished and the inputs may be
+ *    reused. A handle must not be used from two threads at once.
+ *  - st_update is transactional: on any error the decomposition is unchanged.
+ */
+#ifndef STUCKER_H
+#define STUCKER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ST_MAX_MODES 8
+
+enum st_status {
+  ST_OK = 0,
+  ST_EINVAL = -1,       /* bad argument (shape, tolerance, pointer, mode index) */
+  ST_ENOMEM = -2,       /* device or host allocation failed */
+  ST_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+  ST_ESTATE = -4,       /* wrong call order (update before init, init twice) */
+  ST_ENONFINITE = -5,   /* the input holds NaN or Inf (detected before any change) */
+  ST_EDEGENERATE = -6,  /* the initial data is zero: S > 0 cannot hold */
+  ST_ESMALL = -7,       /* caller buffer too small; the required size is returned */
+  ST_ECAPACITY = -8,    /* a rank exceeded a configured cap */
+  ST_ESOLVER = -9       /* a small dense eigensolver reported failure */
+};
+
+enum st_precision {
+  ST_FP32 = 0,   /* TTM chain and Gram products as FP32 MFMA, FP32 accumulation */
+  ST_BF16X3 = 1  /* the same products as split-BF16 (hi*hi + hi*lo + lo*hi) MFMA */
+};
+
+enum st_where { ST_HOST = 0, ST_DEVICE = 1 };
+
+typedef struct st_config {
+  int32_t nmodes;              /* d - 1: number of slice modes, 1..ST_MAX_MODES */
+  int64_t dims[ST_MAX_MODES];  /* n_1 .. n_{d-1}, each >= 1 */
+  double tau;                  /* relative error tolerance (the paper's tau), > 0 */
+  int32_t precision;           /* enum st_precision */
+  double orth_tol;             /* eps_m of the ISVD orthogonality check; 0 = 1e-5 */
+  double guard_rel;            /* relative guard band around each threshold test in
+                                  which the test is re-evaluated in FP32; 0 = default */
+  int64_t max_rank_d;          /* cap on the streaming rank r_d; 0 = no cap */
+  void *stream;                /* hipStream_t to run on; NULL = library-owned stream */
+  int32_t profile;             /* nonzero: time every kernel group with HIP events */
+} st_config;
+
+/* Kernel groups timed when st_config.profile is set. */
+enum st_kernel_group {
+  ST_K_TTM1 = 0,      /* mode-1 projection + residual norm (Alg. 4, first lines) */
+  ST_K_TTM = 1,       /* projection + residual norm of modes 2..d-1 */
+  ST_K_GRAM = 2,      /* residual Gram (Alg. 1 on E_k) */
+  ST_K_EIG = 3,       /* FP64 symmetric eigendecomposition of a Gram */
+  ST_K_TTM_EXT = 4,   /* extended projection with [U_k W_k] after growth */
+  ST_K_ISVD = 5,      /* the three passes over V that form p, e and q (Alg. 3) */
+  ST_K_SVD = 6,       /* secular-equation SVD of S' */
+  ST_K_ROT_V = 7,     /* V~ = [V v] V'' (mode-d TTM) */
+  ST_K_ROT_C = 8,     /* core update, a mode-d TTM of [C; d] */
+  ST_K_UD = 9,        /* U~_d update */
+  ST_K_GROUPS = 10
+};
+
+/* Accumulated timing of one kernel group since the last reset: launches, total
+ * device time (ms, from HIP events on the handle's stream), and the algorithmic
+ * flops and HBM bytes of those launches (the minimum the operation needs). */
+typedef struct st_kernel_profile {
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} st_kernel_profile;
+
+/* Per-slice diagnostics of the last st_update (or of st_init). */
+typedef struct st_slice_stats {
+  double ynorm;                       /* ||Y||_F */
+  double eps;                         /* tau ||Y|| / sqrt(d) (Alg. 5, first step) */
+  double e_norm[ST_MAX_MODES];        /* ||E_k||_F of Alg. 4 per slice mode */
+  int32_t grew[ST_MAX_MODES];         /* new columns r'_k added to U_k */
+  double q;                           /* ||e|| of Alg. 3 */
+  int32_t isvd_ignored;               /* 1 if q <= eps (e ignored) */
+  int32_t qr_fired;                   /* 1 if the orthogonality check fired */
+  int32_t guard_hits;                 /* threshold tests re-evaluated in FP32 */
+  double orth_check;                  /* max_j |V(:,j)^T v| before any QR fix */
+  double delta2;                      /* squared error this slice adds to the bound */
+  double ms_total;                    /* wall time of the call, ms */
+  double ms_modes;                    /* non-streaming modes (Alg. 4), ms */
+  double ms_isvd;                     /* streaming mode (Alg. 3 + core update), ms */
+} st_slice_stats;
+
+typedef struct st_handle st_handle;
+
+/* Create an empty handle and allocate its fixed device state (factors U_k at
+ * full capacity n_k x n_k). Ownership: the handle owns all device memory until
+ * st_destroy. Errors: ST_EINVAL (bad dims, tau <= 0, nmodes out of range),
+ * ST_ENOMEM, ST_EHIP. */
+int st_create(const st_config *cfg, st_handle **out);
+
+/* Initial decomposition (Alg. 2, ST-HOSVD with the streaming mode processed
+ * last) of x0: device float32, column-major n_1 x ... x n_{d-1} x n_init. Sets
+ * S = sqrt of the leading Gram eigenvalues of the last mode and V = A^T U_d S^-1
+ * with A the mode-d unfolding of the last partial core (Alg. 1 optional rows,
+ * Sec. 3.2), so that C = V x_d S (Assumption 1). Errors: ST_ESTATE (already
+ * initialised), ST_EINVAL (n_init < 1), ST_ENONFINITE, ST_EDEGENERATE
+ * (||x0|| = 0), ST_ESOLVER, ST_ENOMEM, ST_EHIP. */
+int st_init(st_handle *h, const float *x0, int64_t n_init);
+
+/* One streaming update (Alg. 5) with the slice y: device float32, column-major
+ * n_1 x ... x n_{d-1}. Runs Alg. 4 for modes 1..d-1, then Alg. 3 on the
+ * streaming mode and the core update. Errors: ST_ESTATE (not initialised),
+ * ST_ENONFINITE, ST_ECAPACITY, ST_ESOLVER, ST_ENOMEM, ST_EHIP; in every error
+ * case the decomposition is unchanged. */
+int st_update(st_handle *h, const float *y);
+
+/* Current ranks r_1..r_d (ranks[0..d-1]) and the number of slices n_d seen. */
+int st_ranks(const st_handle *h, int64_t *ranks, int64_t *n_d);
+
+/* Dense core C (r_1 x ... x r_d, column-major, float32) into out (host or
+ * device pointer per `where`). out == NULL only sets *need (elements).
+ * Errors: ST_ESMALL (cap < need; *need is set), ST_ESTATE, ST_EINVAL. */
+int st_core(const st_handle *h, float *out, int64_t cap, int64_t *need, int where);
+
+/* Dense factor U_mode (mode 0..d-1; mode d-1 is the streaming factor of size
+ * n_d x r_d), column-major float64, into out (host or device). out == NULL only
+ * sets *rows and *cols. Errors: ST_EINVAL, ST_ESMALL, ST_ESTATE. */
+int st_factor(const st_handle *h, int mode, double *out, int64_t cap,
+              int64_t *rows, int64_t *cols, int where);
+
+/* The diagonal S (r_d values, descending) of C = V x_d S into host memory. */
+int st_sv(const st_handle *h, double *s, int64_t cap, int64_t *count);
+
+/* Certified bound on ||X - X^||_F / ||X||_F: sqrt(sum of discarded energy) over
+ * ||X||, where the discarded energy is the ST-HOSVD tails at init (Sec. 2.3)
+ * plus, per slice, the per-mode residuals of Prop. 3 and q^2 when the ISVD
+ * ignores e (Prop. 1, App. D). norm_x = ||X||_F of all data seen. */
+int st_recon_error(const st_handle *h, double *rel_bound, double *norm_x);
+
+/* Diagnostics of the last st_update (or st_init). */
+int st_stats(const st_handle *h, st_slice_stats *out);
+
+/* Slice t (0-based, t < n_d) of the reconstruction C x_1 U_1 ... x_d U_d,
+ * written as float32 column-major n_1 x ... x n_{d-1} to the device pointer
+ * out. Errors: ST_EINVAL (t out of range), ST_ESTATE. */
+int st_reconstruct_slice(const st_handle *h, int64_t t, float *out);
+
+/* Stateless mode-k TTM (Sec. 2.1): out = X x_mode A, for X a dense
+ * column-major float32 device tensor of shape dims[0..nmodes-1] and A a float32
+ * device matrix of shape rows x dims[mode] stored row-major (equivalently A^T
+ * column-major, so a factor U with orthonormal columns passed as `a` gives the
+ * projection X x_mode U^T). out is the column-major device tensor with
+ * dims[mode] replaced by rows. If norms (host, 2 doubles) is not NULL it
+ * receives ||X - (X x_mode A) x_mode A^T||_F^2 and ||X||_F^2 in FP64, the
+ * residual and norm of Alg. 4 (rows <= 256 then). precision: enum
+ * st_precision. stream: hipStream_t or NULL for the default stream; the call
+ * returns after the work has finished. Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
+int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
+           int64_t rows, float *out, double *norms, int32_t precision, void *stream);
+
+/* Stateless mode-k Gram (Alg. 1, first line) of a dense column-major float32
+ * device tensor: G = E_(mode) E_(mode)^T with E = X - (X x_mode A) x_mode A^T
+ * (the residual of Alg. 4) when rows > 0, or E = X when rows == 0; A is a
+ * rows x dims[mode] row-major float32 device matrix (may be NULL when rows == 0).
+ * G is written to the host array g (dims[mode]^2 doubles, column-major).
+ * gram_precision: 0 = FP32 products, 1 = bf16x3 products, 2 = FP64 products (the
+ * residual is always formed with FP32 products). dims[mode] <= 512, rows <= 256.
+ * Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
+int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
+            int64_t rows, double *g, int32_t gram_precision, void *stream);
+
+/* Copy the per-group profile (ST_K_GROUPS entries) into out; reset = 1 also
+ * clears the counters. Errors: ST_EINVAL. */
+int st_profile(st_handle *h, st_kernel_profile *out, int32_t count, int32_t reset);
+
+/* Free every resource of the handle (NULL is allowed). */
+void st_destroy(st_handle *h);
+
+/* Message for the last failure on h (or of the last st_create when h is NULL). */
+const char *st_last_error(const st_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STUCKER_H */

@@ -1,0 +1,145 @@
+// Shared definitions for the gfx950 streaming-Tucker kernels and the engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+namespace st {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+
+// Precision of the TTM / Gram contractions.
+enum class Prec : int { FP32 = 0, BF16X3 = 1 };
+
+// ---------------------------------------------------------------------------
+// Wavefront reductions (64 lanes).
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ inline double wave_prod(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v *= __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Block-wide sum of one double per thread; result valid in every thread.
+// `scratch` must hold blockDim.x / 64 doubles.
+__device__ inline double block_sum(double v, double *scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += scratch[w];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Mapping of a column-major multi-index between two rank tuples.
+//
+// After Alg. 4 pads the core and V with zero slices along the slice modes, a
+// row index of the mode-d matricization at the new ranks r~ addresses either
+// an old row (all i_k < r_k) or a padded (zero) row.
+// ---------------------------------------------------------------------------
+struct RowMap {
+  int nm;                      // number of slice modes
+  int identity;                // 1: new index == old index
+  int32_t r_old[8];
+  int32_t r_new[8];
+};
+
+__host__ __device__ inline int64_t map_new_to_old(const RowMap &m, int64_t row) {
+  if (m.identity) return row;
+  int64_t old = 0, stride = 1;
+  for (int k = 0; k < m.nm; ++k) {
+    const int64_t rn = m.r_new[k];
+    const int64_t ik = row % rn;
+    row /= rn;
+    if (ik >= m.r_old[k]) return -1;
+    old += ik * stride;
+    stride *= m.r_old[k];
+  }
+  return old;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host functions; each enqueues kernels on `stream`).
+// ---------------------------------------------------------------------------
+
+// Addressing of a tensor viewed as `F` fibres of length `n`:
+//  STRIDED: fibre f = i + a*l (i < a) starts at (f % a) + a*n*(f / a);
+//           element j sits at base + a*j. (a = 1: contiguous fibres.)
+//  MAPPED : fibre f starts at map(f) (or is all-zero if map(f) < 0); element
+//           j at base + a*j, and element j == n (one extra element) is taken
+//           from `extra[f]` when `extra` is not null.
+struct FiberIn {
+  const float *x;
+  int64_t a;        // element stride
+  int64_t n;        // fibre length (without the extra element)
+  int64_t F;        // number of fibres
+  int mapped;       // 0: STRIDED, 1: MAPPED
+  RowMap map;
+  const float *extra;  // MAPPED only: optional element n of every fibre
+};
+
+// Output P[f][m] of a fibre contraction at (f % ao) + ao*m + ao*mo*(f / ao).
+struct FiberOut {
+  float *p;
+  int64_t ao;
+  int64_t mo;
+};
+
+// P[f][m] = sum_j X[f][j] * W[m][j] for m in [m0, m0 + mcount); W is row-major
+// with leading dimension ldw over j (K = n, or n + 1 with an extra element).
+// When `resid_partials` is not null (STRIDED only, m0 = 0, mcount = all rows of
+// W), also computes E = X - P x W^T per fibre and writes per-block FP64
+// partial sums {sum E^2, sum X^2} to resid_partials[2 * block].
+// `w_hi`/`w_lo` are the bf16 splits of W (row-major, ld = ldw_bf) for BF16X3.
+struct FiberW {
+  const float *w;
+  int64_t ldw;
+  const __bf16 *w_hi;
+  const __bf16 *w_lo;
+  int64_t ldw_bf;
+};
+
+int fiber_blocks(int64_t F);
+hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int mcount,
+                                const FiberOut &out, double *resid_partials, Prec prec,
+                                hipStream_t s);
+
+// Gram of the residual E = X - (X x W^T) x W (or of X itself when rows == 0)
+// over all fibres: writes per-block partials of the lower-triangular 16x16
+// tiles; `gram_reduce` sums them in FP64 into G (n x n, column-major). The
+// residual is formed with FP32 products; the Gram products use `gp`.
+enum class GramPrec : int { FP32 = 0, BF16X3 = 1, FP64 = 2 };
+int gram_blocks(int64_t F);
+size_t gram_partial_elems(int64_t n, int nblocks);
+hipError_t launch_gram(const FiberIn &in, const FiberW &w, int rows, double *partials,
+                       int nblocks, GramPrec gp, hipStream_t s);
+hipError_t launch_gram_reduce(const double *partials, int nblocks, int64_t n, double *G,
+                              hipStream_t s);
+
+// Sum `count` pairs of FP64 partials into out[0], out[1] (fixed order).
+hipError_t launch_reduce_pairs(const double *partials, int count, double *out, hipStream_t s);
+
+}  // namespace st

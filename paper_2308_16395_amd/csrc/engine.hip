@@ -1,0 +1,1164 @@
+// Streaming Tucker engine: device state, the initial ST-HOSVD (Alg. 2) and the
+// per-slice update (Alg. 5 = Alg. 4 on every slice mode, then Alg. 3 on the
+// streaming mode and the core update), behind the C ABI of stucker.h.
+//
+// Host code only orchestrates: every arithmetic step of the update runs in the
+// kernels of k_fiber.hip / k_isvd.hip, except the small symmetric
+// eigendecompositions of the Gram matrices, which run on the device through
+// rocSOLVER (FP64). The host reads back the scalars that decide the branches
+// (norms, eigenvalues for the rank rule) and the new ranks.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stucker.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "secular.hpp"
+
+using namespace st;
+
+namespace {
+
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= cap && p) return hipSuccess;
+    size_t want = std::max(n, cap + cap / 2);
+    if (want == 0) want = 1;
+    T *q = nullptr;
+    hipError_t e = hipMalloc((void **)&q, want * sizeof(T));
+    if (e != hipSuccess) {
+      want = n > 0 ? n : 1;
+      e = hipMalloc((void **)&q, want * sizeof(T));
+      if (e != hipSuccess) return e;
+    }
+    if (p) (void)hipFree(p);
+    p = q;
+    cap = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+thread_local std::string g_create_error;
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// Rank rule of Alg. 1 on eigenvalues given in ascending order: descending
+// order, negative round-off clamped to zero, tail sums from the smallest up,
+// r = min{l : tail(l) <= eps^2}. Returns r and tail(r).
+void rank_rule(const double *lam_asc, int64_t n, double eps, int64_t &r, double &tail_r,
+               std::vector<double> &desc) {
+  desc.resize(n);
+  for (int64_t i = 0; i < n; ++i) desc[i] = std::max(lam_asc[n - 1 - i], 0.0);
+  std::vector<double> tail(n + 1, 0.0);
+  for (int64_t l = n - 1; l >= 0; --l) tail[l] = tail[l + 1] + desc[l];
+  const double e2 = eps * eps;
+  r = n;
+  for (int64_t l = 0; l <= n; ++l)
+    if (tail[l] <= e2) {
+      r = l;
+      break;
+    }
+  tail_r = tail[r];
+}
+
+}  // namespace
+
+struct st_handle {
+  // configuration
+  int m = 0;  // slice modes
+  int64_t n[ST_MAX_MODES] = {};
+  int64_t NY = 0;
+  double tau = 0.0;
+  Prec prec = Prec::FP32;
+  double orth_tol = 1e-5;
+  double guard_rel = 0.0;
+  int64_t max_rank_d = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  rocblas_handle rb = nullptr;
+  std::string err;
+
+  // decomposition
+  bool inited = false;
+  int64_t r[ST_MAX_MODES] = {};
+  int64_t rd = 0, nd = 0;
+  double xnorm2 = 0.0, disc = 0.0;
+  std::vector<double> S_host;
+  st_slice_stats stats{};
+
+  // factors of the slice modes (capacity n_k columns)
+  double *U64[ST_MAX_MODES] = {};
+  float *Uf[ST_MAX_MODES] = {};
+  float *Ut[ST_MAX_MODES] = {};
+  __bf16 *Uh[ST_MAX_MODES] = {};
+  __bf16 *Ul[ST_MAX_MODES] = {};
+  int64_t ldb[ST_MAX_MODES] = {};
+
+  // streaming-mode state (ping-pong)
+  DBuf<double> Ud[2];
+  int64_t ud_ld[2] = {0, 0};
+  DBuf<double> S[2];
+  DBuf<float> V[2], C[2];
+  int cur = 0;
+
+  // work buffers
+  DBuf<float> D[2], evec, wrow;
+  DBuf<double> part, sums;
+  DBuf<double> gram_part;
+  DBuf<double> G, eigval, eigwork, Wnew, coef;
+  DBuf<int> info;
+  DBuf<double> colpart, q2part, p1, p2, p, p3;
+  DBuf<double> U2, V2;
+  DBuf<float> Wv, Wc;
+  // secular scratch
+  DBuf<double> sd, sz, szh, smu, srot_cs, szz;
+  DBuf<int> sact, sK, sdefl, sorg, srot_t, scounts;
+  double *hpin = nullptr;  // pinned host scratch
+  size_t hpin_cap = 0;
+
+  // optional per-group timing with HIP events on `stream`
+  bool profile = false;
+  st_kernel_profile prof[ST_K_GROUPS] = {};
+  struct Pending {
+    int group;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // Bracket a launch sequence: tic() before, toc(group, flops, bytes) after.
+  hipEvent_t tic_ev = nullptr;
+  void tic() {
+    if (!profile) return;
+    tic_ev = get_event();
+    if (tic_ev) (void)hipEventRecord(tic_ev, stream);
+  }
+  void toc(int group, double flops, double bytes) {
+    if (!profile || !tic_ev) return;
+    hipEvent_t b = get_event();
+    if (!b) return;
+    (void)hipEventRecord(b, stream);
+    pending.push_back(Pending{group, tic_ev, b, flops, bytes});
+    tic_ev = nullptr;
+  }
+  // After a stream synchronisation: fold finished intervals into the counters.
+  void settle() {
+    for (auto &pd : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+        prof[pd.group].launches += 1;
+        prof[pd.group].ms += ms;
+        prof[pd.group].flops += pd.flops;
+        prof[pd.group].bytes += pd.bytes;
+      }
+      event_pool.push_back(pd.a);
+      event_pool.push_back(pd.b);
+    }
+    pending.clear();
+  }
+
+  int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+
+  int hipfail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory)
+      return fail(ST_ENOMEM, "%s: out of device memory", what);
+    return fail(ST_EHIP, "%s: %s", what, hipGetErrorString(e));
+  }
+
+  FiberW wmat(int k) const {
+    FiberW w{};
+    w.w = Uf[k];
+    w.ldw = n[k];
+    w.w_hi = Uh[k];
+    w.w_lo = Ul[k];
+    w.ldw_bf = ldb[k];
+    return w;
+  }
+
+  int64_t rprod(const int64_t *rr, int upto) const {
+    int64_t p_ = 1;
+    for (int k = 0; k < upto; ++k) p_ *= rr[k];
+    return p_;
+  }
+  int64_t nprod(int from) const {
+    int64_t p_ = 1;
+    for (int k = from; k < m; ++k) p_ *= n[k];
+    return p_;
+  }
+
+  hipError_t ensure_pinned(size_t count) {
+    if (count <= hpin_cap) return hipSuccess;
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = nullptr;
+    hpin_cap = 0;
+    hipError_t e = hipHostMalloc((void **)&hpin, count * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) hpin_cap = count;
+    return e;
+  }
+
+  // Number of blocks launch_fiber_project uses for F fibres (norm partials).
+  static int fiber_nblocks(int64_t F) {
+    return (int)(F >= 256 * 128 ? (F + 127) / 128 : (F + 63) / 64);
+  }
+
+  // Norms of E and X for mode k into hpin[0..1].
+  int project_resid(const FiberIn &in, const FiberW &w, int rows, const FiberOut &out, Prec pr,
+                    int group) {
+    const int nb = fiber_nblocks(in.F);
+    hipError_t e = part.ensure(2 * (size_t)nb);
+    if (e != hipSuccess) return hipfail(e, "partials");
+    tic();
+    e = launch_fiber_project(in, w, 0, rows, out, part.p, pr, stream);
+    if (e != hipSuccess) return hipfail(e, "fiber projection + residual");
+    // P = D x_k U^T and E = D - P x_k U: 4 F n r flops; D read once, P written once
+    toc(group, 4.0 * in.F * in.n * rows, 4.0 * in.F * (in.n + rows));
+    e = launch_reduce_pairs(part.p, nb, sums.p, stream);
+    if (e != hipSuccess) return hipfail(e, "reduce");
+    e = hipMemcpyAsync(hpin, sums.p, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "residual norms");
+    settle();
+    return ST_OK;
+  }
+
+  // Gram of the residual (rows > 0) or of the tensor (rows == 0) for fibres of
+  // length nk, then its eigendecomposition; eigenvalues (ascending) land in
+  // hpin[0..nk), eigenvectors in G.
+  int gram_eig(const FiberIn &in, const FiberW &w, int rows, int64_t nk, GramPrec pr) {
+    const int gnb = gram_blocks(in.F);
+    hipError_t e = gram_part.ensure(gram_partial_elems(nk, gnb));
+    if (e == hipSuccess) e = G.ensure((size_t)nk * nk);
+    if (e == hipSuccess) e = eigval.ensure(nk);
+    if (e == hipSuccess) e = eigwork.ensure(nk);
+    if (e == hipSuccess) e = info.ensure(1);
+    if (e == hipSuccess) e = ensure_pinned(nk + 8);
+    if (e != hipSuccess) return hipfail(e, "gram buffers");
+    tic();
+    e = launch_gram(in, w, rows, gram_part.p, gnb, pr, stream);
+    if (e != hipSuccess) return hipfail(e, "gram");
+    // recompute E (4 F n r) and form the lower triangle of E E^T (F n^2)
+    toc(ST_K_GRAM, 4.0 * in.F * nk * rows + 1.0 * in.F * nk * nk, 4.0 * in.F * nk);
+    e = launch_gram_reduce(gram_part.p, gnb, nk, G.p, stream);
+    if (e != hipSuccess) return hipfail(e, "gram reduce");
+    tic();
+    rocblas_status rs = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_lower,
+                                         (rocblas_int)nk, G.p, (rocblas_int)nk, eigval.p,
+                                         eigwork.p, info.p);
+    toc(ST_K_EIG, 9.0 * nk * nk * nk, 16.0 * nk * nk);
+    if (rs != rocblas_status_success) return fail(ST_ESOLVER, "rocsolver_dsyevd status %d", rs);
+    e = hipMemcpyAsync(hpin, eigval.p, nk * sizeof(double), hipMemcpyDeviceToHost, stream);
+    int hinfo = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "eigenvalues");
+    settle();
+    if (hinfo != 0) return fail(ST_ESOLVER, "rocsolver_dsyevd info %d", hinfo);
+    for (int64_t i = 0; i < nk; ++i)
+      if (!std::isfinite(hpin[i])) return fail(ST_ENONFINITE, "non-finite Gram eigenvalue");
+    return ST_OK;
+  }
+
+  int append_columns(int k, int64_t c0, int64_t cnt) {
+    const int64_t nk = n[k];
+    hipError_t e = Wnew.ensure((size_t)nk * cnt);
+    if (e == hipSuccess) e = coef.ensure((size_t)std::max<int64_t>(c0, 1) * cnt);
+    if (e != hipSuccess) return hipfail(e, "new columns");
+    e = launch_new_columns(G.p, nk, U64[k], (int)c0, (int)cnt, Wnew.p, coef.p, stream);
+    if (e != hipSuccess) return hipfail(e, "reorthogonalise new columns");
+    e = launch_append_cols(Wnew.p, nk, (int)c0, (int)cnt, U64[k], Uf[k], Ut[k], Uh[k], Ul[k],
+                           ldb[k], stream);
+    if (e != hipSuccess) return hipfail(e, "append columns");
+    return ST_OK;
+  }
+
+  SecData secdata(int rr) {
+    SecData s{};
+    s.n = rr + 1;
+    s.r = rr;
+    s.d = sd.p;
+    s.z = sz.p;
+    s.zh = szh.p;
+    s.active = sact.p;
+    s.K = sK.p;
+    s.defl = sdefl.p;
+    s.org = sorg.p;
+    s.mu = smu.p;
+    s.rot_t = srot_t.p;
+    s.rot_cs = srot_cs.p;
+    s.counts = scounts.p;
+    s.zz = szz.p;
+    return s;
+  }
+
+  hipError_t ensure_secular(int64_t nn) {
+    hipError_t e = sd.ensure(nn);
+    if (e == hipSuccess) e = sz.ensure(nn);
+    if (e == hipSuccess) e = szh.ensure(nn);
+    if (e == hipSuccess) e = smu.ensure(nn);
+    if (e == hipSuccess) e = srot_cs.ensure(2 * nn);
+    if (e == hipSuccess) e = szz.ensure(1);
+    if (e == hipSuccess) e = sact.ensure(nn);
+    if (e == hipSuccess) e = sK.ensure(nn);
+    if (e == hipSuccess) e = sdefl.ensure(nn);
+    if (e == hipSuccess) e = sorg.ensure(nn);
+    if (e == hipSuccess) e = srot_t.ensure(2 * nn);
+    if (e == hipSuccess) e = scounts.ensure(4);
+    return e;
+  }
+
+  int do_init(const float *x0, int64_t n_init);
+  int do_update(const float *y);
+  int do_reconstruct_slice(int64_t t, float *out);
+  void destroy();
+};
+
+// ---------------------------------------------------------------------------
+// Alg. 2 with the streaming mode processed last.
+// ---------------------------------------------------------------------------
+int st_handle::do_init(const float *x0, int64_t n_init) {
+  const auto t0 = clk::now();
+  if (inited) return fail(ST_ESTATE, "already initialised");
+  if (x0 == nullptr || n_init < 1) return fail(ST_EINVAL, "bad initial data");
+  const int d = m + 1;
+  const int64_t N0 = NY * n_init;
+  hipError_t e = ensure_pinned(256);
+  if (e != hipSuccess) return hipfail(e, "pinned buffer");
+
+  // ||X0||^2 in FP64
+  {
+    const int nb = 1024;
+    e = part.ensure(2 * nb);
+    if (e != hipSuccess) return hipfail(e, "partials");
+    e = launch_sumsq(x0, N0, part.p, nb, stream);
+    if (e == hipSuccess) e = launch_reduce_pairs(part.p, nb, sums.p, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hpin, sums.p, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "norm of initial data");
+  }
+  const double xn2 = hpin[0];
+  if (!std::isfinite(xn2)) return fail(ST_ENONFINITE, "initial data is not finite");
+  if (xn2 == 0.0) return fail(ST_EDEGENERATE, "initial data is zero");
+  const double eps = tau * std::sqrt(xn2 / d);
+
+  int64_t rr[ST_MAX_MODES] = {};
+  double tails = 0.0;
+  std::vector<double> desc;
+  DBuf<float> T[2];
+  const float *Din = x0;
+  int sel = 0;
+  int rc = ST_OK;
+  for (int k = 0; k <= m && rc == ST_OK; ++k) {
+    const int64_t a = rprod(rr, k);
+    const int64_t nk = (k < m) ? n[k] : n_init;
+    const int64_t b = (k < m) ? nprod(k + 1) * n_init : 1;
+    FiberIn in{};
+    in.x = Din;
+    in.a = a;
+    in.n = nk;
+    in.F = a * b;
+    // Gram of the data itself: eigenvalues near eps^2 = tau^2 ||X||^2 / d must
+    // be resolved, so the products are accumulated exactly in FP64.
+    rc = gram_eig(in, FiberW{}, 0, nk, GramPrec::FP64);
+    if (rc != ST_OK) break;
+    int64_t rk;
+    double tail;
+    rank_rule(hpin, nk, eps, rk, tail, desc);
+    if (k == m && max_rank_d > 0 && rk > max_rank_d) {
+      rc = fail(ST_ECAPACITY, "initial streaming rank %lld exceeds the cap", (long long)rk);
+      break;
+    }
+    if (rk == 0) {
+      rc = fail(ST_EDEGENERATE, "rank 0 in mode %d", k + 1);
+      break;
+    }
+    // the discarded tail with the chosen rank
+    tail = 0.0;
+    for (int64_t i = rk; i < nk; ++i) tail += desc[i];
+    tails += tail;
+    if (k < m) {
+      rc = append_columns(k, 0, rk);
+      if (rc != ST_OK) break;
+      rr[k] = rk;
+      e = T[sel].ensure((size_t)(a * rk * b));
+      if (e != hipSuccess) {
+        rc = hipfail(e, "init partial core");
+        break;
+      }
+      FiberOut out{T[sel].p, a, rk};
+      e = launch_fiber_project(in, wmat(k), 0, (int)rk, out, nullptr, prec, stream);
+      if (e != hipSuccess) {
+        rc = hipfail(e, "init projection");
+        break;
+      }
+      Din = T[sel].p;
+      sel ^= 1;
+    } else {
+      const int64_t R = a;
+      rd = rk;
+      nd = n_init;
+      const int64_t ldu = round_up(std::max<int64_t>(2 * n_init, 64), 64);
+      e = Ud[cur].ensure((size_t)ldu * std::max<int64_t>(rk, 1));
+      if (e == hipSuccess) e = Wnew.ensure((size_t)nk * rk);
+      if (e == hipSuccess) e = S[cur].ensure(rk);
+      if (e != hipSuccess) {
+        rc = hipfail(e, "streaming factor");
+        break;
+      }
+      ud_ld[cur] = ldu;
+      e = launch_new_columns(G.p, nk, nullptr, 0, (int)rk, Wnew.p, nullptr, stream);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(Ud[cur].p, ldu * sizeof(double), Wnew.p, nk * sizeof(double),
+                             nk * sizeof(double), rk, hipMemcpyDeviceToDevice, stream);
+      S_host.assign(rk, 0.0);
+      for (int64_t i = 0; i < rk; ++i) S_host[i] = std::sqrt(desc[i]);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(S[cur].p, S_host.data(), rk * sizeof(double), hipMemcpyHostToDevice,
+                           stream);
+      const int64_t ldw = round_up(n_init, 4);
+      if (e == hipSuccess) e = Wv.ensure((size_t)rk * ldw);
+      if (e == hipSuccess) e = Wc.ensure((size_t)rk * ldw);
+      if (e == hipSuccess) e = V[cur].ensure((size_t)(R * rk));
+      if (e == hipSuccess) e = C[cur].ensure((size_t)(R * rk));
+      if (e == hipSuccess)
+        e = launch_build_init_w(Ud[cur].p, ldu, n_init, (int)rk, S[cur].p, Wv.p, Wc.p, ldw,
+                                stream);
+      if (e != hipSuccess) {
+        rc = hipfail(e, "streaming factor");
+        break;
+      }
+      // V = A^T U_d S^-1 and C_(d)^T = A^T U_d, A = C*_{d-1,(d)} (rows = fibres)
+      FiberW wv{};
+      wv.w = Wv.p;
+      wv.ldw = ldw;
+      FiberW wc{};
+      wc.w = Wc.p;
+      wc.ldw = ldw;
+      e = launch_fiber_project(in, wv, 0, (int)rk, FiberOut{V[cur].p, R, rk}, nullptr,
+                               Prec::FP32, stream);
+      if (e == hipSuccess)
+        e = launch_fiber_project(in, wc, 0, (int)rk, FiberOut{C[cur].p, R, rk}, nullptr,
+                                 Prec::FP32, stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) {
+        rc = hipfail(e, "init core");
+        break;
+      }
+    }
+  }
+  T[0].release();
+  T[1].release();
+  if (rc != ST_OK) {
+    for (int k = 0; k < m; ++k) r[k] = 0;
+    rd = nd = 0;
+    return rc;
+  }
+  for (int k = 0; k < m; ++k) r[k] = rr[k];
+  xnorm2 = xn2;
+  disc = tails;
+  inited = true;
+  stats = st_slice_stats{};
+  stats.ynorm = std::sqrt(xn2);
+  stats.eps = eps;
+  stats.delta2 = tails;
+  stats.ms_total = ms_since(t0);
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 5.
+// ---------------------------------------------------------------------------
+int st_handle::do_update(const float *y) {
+  const auto t0 = clk::now();
+  if (!inited) return fail(ST_ESTATE, "update before init");
+  if (y == nullptr) return fail(ST_EINVAL, "null slice");
+  const int d = m + 1;
+  st_slice_stats stt{};
+  int64_t rn[ST_MAX_MODES];
+  for (int k = 0; k < m; ++k) rn[k] = r[k];
+  hipError_t e = ensure_pinned(2 * (size_t)std::max<int64_t>(rd + 2, 64) + 64);
+  if (e != hipSuccess) return hipfail(e, "pinned buffer");
+
+  std::vector<double> desc;
+  const float *Din = y;
+  int dsel = 0;
+  double delta2 = 0.0, eps = 0.0, ynorm2 = 0.0;
+  int rc;
+  for (int k = 0; k < m; ++k) {
+    const int64_t a = rprod(rn, k);
+    const int64_t nk = n[k];
+    const int64_t b = nprod(k + 1);
+    FiberIn in{};
+    in.x = Din;
+    in.a = a;
+    in.n = nk;
+    in.F = a * b;
+    float *Dout = D[dsel].p;
+    const int tgroup = k == 0 ? ST_K_TTM1 : ST_K_TTM;
+    rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, a, r[k]}, prec, tgroup);
+    if (rc != ST_OK) return rc;
+    double e2 = hpin[0];
+    if (k == 0) {
+      ynorm2 = hpin[1];
+      if (!std::isfinite(ynorm2)) return fail(ST_ENONFINITE, "slice is not finite");
+      eps = tau * std::sqrt(ynorm2 / d);
+    }
+    if (!std::isfinite(e2)) return fail(ST_ENONFINITE, "non-finite residual in mode %d", k + 1);
+    if (prec == Prec::BF16X3 && std::fabs(std::sqrt(e2) - eps) <= guard_rel * eps) {
+      // close to the threshold: decide with the FP32 products
+      rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, a, r[k]}, Prec::FP32, tgroup);
+      if (rc != ST_OK) return rc;
+      e2 = hpin[0];
+      ++stt.guard_hits;
+    }
+    stt.e_norm[k] = std::sqrt(e2);
+    if (std::sqrt(e2) <= eps) {  // Alg. 4: keep U_k, D*_k = P_k
+      delta2 += e2;
+      Din = Dout;
+      dsel ^= 1;
+      continue;
+    }
+    // Alg. 4 growth: TruncatedSVD of E_(k) via its Gram (Alg. 1)
+    rc = gram_eig(in, wmat(k), (int)r[k], nk,
+                  prec == Prec::BF16X3 ? GramPrec::BF16X3 : GramPrec::FP32);
+    if (rc != ST_OK) return rc;
+    int64_t rp;
+    double tail;
+    rank_rule(hpin, nk, eps, rp, tail, desc);
+    rp = std::min<int64_t>(rp, nk - r[k]);
+    if (rp <= 0) {  // the Gram resolves nothing above the tolerance
+      delta2 += e2;
+      Din = Dout;
+      dsel ^= 1;
+      continue;
+    }
+    tail = 0.0;
+    for (int64_t i = rp; i < nk; ++i) tail += desc[i];
+    delta2 += tail;
+    rc = append_columns(k, r[k], rp);
+    if (rc != ST_OK) return rc;
+    rn[k] = r[k] + rp;
+    stt.grew[k] = (int32_t)rp;
+    // D*_k = D*_{k-1} x_k [U_k W_k]^T
+    tic();
+    e = launch_fiber_project(in, wmat(k), 0, (int)rn[k], FiberOut{Dout, a, rn[k]}, nullptr, prec,
+                             stream);
+    toc(ST_K_TTM_EXT, 2.0 * in.F * nk * rn[k], 4.0 * in.F * (nk + rn[k]));
+    if (e != hipSuccess) return hipfail(e, "extended projection");
+    Din = Dout;
+    dsel ^= 1;
+  }
+  const double ms_modes = ms_since(t0);
+
+  // ---- streaming mode: Alg. 3 on d = vec(D*_{d-1}) ----
+  const int64_t Rold = rprod(r, m), Rnew = rprod(rn, m);
+  RowMap map{};
+  map.nm = m;
+  map.identity = 1;
+  for (int k = 0; k < m; ++k) {
+    map.r_old[k] = (int32_t)r[k];
+    map.r_new[k] = (int32_t)rn[k];
+    if (rn[k] != r[k]) map.identity = 0;
+  }
+  const float *dvec = Din;
+  const int rdi = (int)rd;
+  const int nb = isvd_blocks(Rnew);
+  e = colpart.ensure((size_t)nb * rdi);
+  if (e == hipSuccess) e = q2part.ensure(nb);
+  if (e == hipSuccess) e = p1.ensure(rdi);
+  if (e == hipSuccess) e = p2.ensure(rdi);
+  if (e == hipSuccess) e = p.ensure(rdi);
+  if (e == hipSuccess) e = p3.ensure(rdi);
+  if (e == hipSuccess) e = evec.ensure(Rnew);
+  if (e != hipSuccess) return hipfail(e, "isvd buffers");
+  IsvdArgs ia{};
+  ia.V = V[cur].p;
+  ia.ldv = Rold;
+  ia.r = rdi;
+  ia.R = Rnew;
+  ia.map = map;
+  ia.d = dvec;
+  ia.p1 = p1.p;
+  ia.p2 = p2.p;
+  ia.e = evec.p;
+  ia.colpart = colpart.p;
+  ia.q2part = q2part.p;
+  tic();
+  e = launch_isvd_pass(1, ia, nb, stream);
+  if (e == hipSuccess)
+    e = launch_colsum(colpart.p, nb, rdi, p1.p, nullptr, nullptr, nullptr, nullptr, stream);
+  if (e == hipSuccess) e = launch_isvd_pass(2, ia, nb, stream);
+  if (e == hipSuccess)
+    e = launch_colsum(colpart.p, nb, rdi, p2.p, p1.p, p.p, nullptr, nullptr, stream);
+  if (e == hipSuccess) e = launch_isvd_pass(3, ia, nb, stream);
+  if (e == hipSuccess)
+    e = launch_colsum(colpart.p, nb, rdi, p3.p, nullptr, nullptr, q2part.p, sums.p, stream);
+  // p1 = V^T d; e1 = d - V p1, p2 = V^T e1; e = e1 - V p2, V^T e: 10 R r flops, V read 3x
+  toc(ST_K_ISVD, 10.0 * Rnew * rdi, 3.0 * 4.0 * Rold * rdi + 4.0 * 4.0 * Rnew);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hpin, sums.p, sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hpin + 1, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hpin + 1 + rdi, p3.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
+                       stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "isvd projections");
+  settle();
+  const double q2 = hpin[0];
+  const double q = std::sqrt(std::max(q2, 0.0));
+  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+  double pmax = 0.0, p3max = 0.0;
+  for (int j = 0; j < rdi; ++j) {
+    pmax = std::max(pmax, std::fabs(hpin[1 + j]));
+    p3max = std::max(p3max, std::fabs(hpin[1 + rdi + j]));
+  }
+  const double tol = 8.0 * 0x1p-53 * std::max({S_host.empty() ? 0.0 : S_host[0], pmax, q});
+  const int grow = (q > eps && q > tol) ? 1 : 0;
+  const int64_t c = rd + grow;
+  stt.q = q;
+  stt.isvd_ignored = grow ? 0 : 1;
+  stt.orth_check = q > 0.0 ? p3max / q : 0.0;
+  stt.qr_fired = (grow && stt.orth_check > orth_tol) ? 1 : 0;
+  if (max_rank_d > 0 && c > max_rank_d)
+    return fail(ST_ECAPACITY, "streaming rank %lld exceeds the cap", (long long)c);
+
+  const int nxt = cur ^ 1;
+  const int64_t nn = rd + 1;
+  const int64_t kv = rd + grow;
+  const int64_t ldwv = round_up(kv, 4), ldwc = round_up(rd + 1, 4);
+  e = ensure_secular(nn);
+  if (e == hipSuccess) e = U2.ensure((size_t)nn * c);
+  if (e == hipSuccess) e = V2.ensure((size_t)nn * c);
+  if (e == hipSuccess) e = S[nxt].ensure(c);
+  if (e == hipSuccess) e = Wv.ensure((size_t)c * ldwv);
+  if (e == hipSuccess) e = Wc.ensure((size_t)c * ldwc);
+  if (e == hipSuccess) e = V[nxt].ensure((size_t)(Rnew * c));
+  if (e == hipSuccess) e = C[nxt].ensure((size_t)(Rnew * c));
+  int64_t ldn = ud_ld[nxt];
+  if (e == hipSuccess && (ldn < nd + 1 || Ud[nxt].cap < (size_t)ldn * c)) {
+    ldn = std::max<int64_t>(ud_ld[cur], round_up(nd + 1, 64));
+    if (ldn < nd + 1 + 0) ldn = round_up(2 * (nd + 1), 64);
+    e = Ud[nxt].ensure((size_t)ldn * c);
+  }
+  if (e != hipSuccess) return hipfail(e, "streaming buffers");
+  ud_ld[nxt] = ldn;
+
+  tic();
+  e = launch_secular_svd(secdata(rdi), S[cur].p, p.p, q, grow, tol, (int)c, U2.p, V2.p,
+                         S[nxt].p, stream);
+  if (e == hipSuccess)
+    e = launch_build_rot_w(U2.p, V2.p, rdi, (int)c, (int)kv, grow ? 1.0 / q : 0.0, Wv.p, ldwv,
+                           Wc.p, ldwc, stream);
+  toc(ST_K_SVD, 60.0 * (double)nn * nn, 8.0 * 4.0 * nn * c);
+  if (e != hipSuccess) return hipfail(e, "small SVD");
+  // V~ = [V v] V''  (mode-d TTM of V with the padded rows mapped)
+  FiberIn vin{};
+  vin.x = V[cur].p;
+  vin.a = Rold;
+  vin.n = rd;
+  vin.F = Rnew;
+  vin.mapped = 1;
+  vin.map = map;
+  vin.extra = grow ? evec.p : nullptr;
+  FiberW vw{};
+  vw.w = Wv.p;
+  vw.ldw = ldwv;
+  tic();
+  e = launch_fiber_project(vin, vw, 0, (int)c, FiberOut{V[nxt].p, Rnew, c}, nullptr, Prec::FP32,
+                           stream);
+  // read V (R_old x r_d) and e, write V~ (R_new x c): 2 R_new K c flops
+  toc(ST_K_ROT_V, 2.0 * Rnew * (double)kv * c,
+      4.0 * ((double)Rold * rd + (grow ? Rnew : 0) + (double)Rnew * c));
+  if (e != hipSuccess) return hipfail(e, "V rotation");
+  // C~_(d) = U~_d(1:n_d,:)^T U_d C_(d) + U~_d(n_d+1,:)^T d^T = U''^T [C_(d); d^T]
+  FiberIn cin = vin;
+  cin.x = C[cur].p;
+  cin.extra = dvec;
+  FiberW cw{};
+  cw.w = Wc.p;
+  cw.ldw = ldwc;
+  tic();
+  e = launch_fiber_project(cin, cw, 0, (int)c, FiberOut{C[nxt].p, Rnew, c}, nullptr, Prec::FP32,
+                           stream);
+  toc(ST_K_ROT_C, 2.0 * Rnew * (double)(rd + 1) * c,
+      4.0 * ((double)Rold * rd + Rnew + (double)Rnew * c));
+  if (e != hipSuccess) return hipfail(e, "core rotation");
+  tic();
+  e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
+  toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + 1.0) * c));
+  if (e != hipSuccess) return hipfail(e, "streaming factor update");
+  e = hipMemcpyAsync(hpin, S[nxt].p, c * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "streaming update");
+  settle();
+  for (int64_t i = 0; i < c; ++i)
+    if (!std::isfinite(hpin[i]) || hpin[i] <= 0.0)
+      return fail(ST_ESOLVER, "small SVD produced a non-positive singular value");
+
+  // ---- commit ----
+  S_host.assign(hpin, hpin + c);
+  for (int k = 0; k < m; ++k) r[k] = rn[k];
+  rd = c;
+  nd += 1;
+  cur = nxt;
+  xnorm2 += ynorm2;
+  if (!grow) delta2 += q2;
+  disc += delta2;
+  stt.ynorm = std::sqrt(ynorm2);
+  stt.eps = eps;
+  stt.delta2 = delta2;
+  stt.ms_modes = ms_modes;
+  stt.ms_total = ms_since(t0);
+  stt.ms_isvd = stt.ms_total - ms_modes;
+  stats = stt;
+  return ST_OK;
+}
+
+// Slice t of C x_1 U_1 ... x_d U_d.
+int st_handle::do_reconstruct_slice(int64_t t, float *out) {
+  if (!inited) return fail(ST_ESTATE, "not initialised");
+  if (t < 0 || t >= nd || out == nullptr) return fail(ST_EINVAL, "slice index out of range");
+  const int64_t R = rprod(r, m);
+  hipError_t e = wrow.ensure(round_up(rd, 4));
+  if (e == hipSuccess) e = D[0].ensure(NY);
+  if (e == hipSuccess) e = D[1].ensure(NY);
+  if (e != hipSuccess) return hipfail(e, "reconstruct buffers");
+  e = launch_ud_row(Ud[cur].p, ud_ld[cur], t, (int)rd, wrow.p, stream);
+  FiberIn in{};
+  in.x = C[cur].p;
+  in.a = R;
+  in.n = rd;
+  in.F = R;
+  FiberW w{};
+  w.w = wrow.p;
+  w.ldw = rd;
+  float *cur_buf = (m == 0) ? out : D[0].p;
+  if (e == hipSuccess)
+    e = launch_fiber_project(in, w, 0, 1, FiberOut{cur_buf, R, 1}, nullptr, Prec::FP32, stream);
+  int sel = 1;
+  int64_t shape[ST_MAX_MODES];
+  for (int k = 0; k < m; ++k) shape[k] = r[k];
+  for (int k = m - 1; k >= 0 && e == hipSuccess; --k) {
+    int64_t a = 1, b = 1;
+    for (int l = 0; l < k; ++l) a *= shape[l];
+    for (int l = k + 1; l < m; ++l) b *= shape[l];
+    FiberIn ein{};
+    ein.x = cur_buf;
+    ein.a = a;
+    ein.n = shape[k];
+    ein.F = a * b;
+    FiberW uw{};
+    uw.w = Ut[k];
+    uw.ldw = n[k];
+    float *dst = (k == 0) ? out : D[sel].p;
+    e = launch_fiber_project(ein, uw, 0, (int)n[k], FiberOut{dst, a, n[k]}, nullptr, Prec::FP32,
+                             stream);
+    shape[k] = n[k];
+    cur_buf = dst;
+    sel ^= 1;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "reconstruct slice");
+  return ST_OK;
+}
+
+void st_handle::destroy() {
+  (void)hipSetDevice(device);
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (int k = 0; k < m; ++k) {
+    if (U64[k]) (void)hipFree(U64[k]);
+    if (Uf[k]) (void)hipFree(Uf[k]);
+    if (Ut[k]) (void)hipFree(Ut[k]);
+    if (Uh[k]) (void)hipFree(Uh[k]);
+    if (Ul[k]) (void)hipFree(Ul[k]);
+  }
+  for (int i = 0; i < 2; ++i) {
+    Ud[i].release();
+    S[i].release();
+    V[i].release();
+    C[i].release();
+    D[i].release();
+  }
+  evec.release();
+  wrow.release();
+  part.release();
+  sums.release();
+  gram_part.release();
+  G.release();
+  eigval.release();
+  eigwork.release();
+  Wnew.release();
+  coef.release();
+  info.release();
+  colpart.release();
+  q2part.release();
+  p1.release();
+  p2.release();
+  p.release();
+  p3.release();
+  U2.release();
+  V2.release();
+  Wv.release();
+  Wc.release();
+  sd.release();
+  sz.release();
+  szh.release();
+  smu.release();
+  srot_cs.release();
+  szz.release();
+  sact.release();
+  sK.release();
+  sdefl.release();
+  sorg.release();
+  srot_t.release();
+  scounts.release();
+  if (hpin) (void)hipHostFree(hpin);
+  for (auto &pd : pending) {
+    event_pool.push_back(pd.a);
+    event_pool.push_back(pd.b);
+  }
+  pending.clear();
+  for (hipEvent_t ev : event_pool) (void)hipEventDestroy(ev);
+  event_pool.clear();
+  if (tic_ev) (void)hipEventDestroy(tic_ev);
+  if (rb) rocblas_destroy_handle(rb);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int st_create(const st_config *cfg, st_handle **out) {
+  g_create_error.clear();
+  if (out == nullptr || cfg == nullptr) {
+    g_create_error = "null argument";
+    return ST_EINVAL;
+  }
+  *out = nullptr;
+  if (cfg->nmodes < 1 || cfg->nmodes > ST_MAX_MODES || !(cfg->tau > 0.0) ||
+      !std::isfinite(cfg->tau) || (cfg->precision != ST_FP32 && cfg->precision != ST_BF16X3) ||
+      cfg->max_rank_d < 0) {
+    g_create_error = "invalid configuration";
+    return ST_EINVAL;
+  }
+  int64_t ny = 1;
+  for (int k = 0; k < cfg->nmodes; ++k) {
+    if (cfg->dims[k] < 1 || cfg->dims[k] > (1 << 20)) {
+      g_create_error = "invalid slice dimension";
+      return ST_EINVAL;
+    }
+    ny *= cfg->dims[k];
+  }
+  if (ny > ((int64_t)1 << 34)) {
+    g_create_error = "slice too large";
+    return ST_EINVAL;
+  }
+  st_handle *h = new (std::nothrow) st_handle();
+  if (!h) {
+    g_create_error = "host allocation failed";
+    return ST_ENOMEM;
+  }
+  h->m = cfg->nmodes;
+  for (int k = 0; k < h->m; ++k) h->n[k] = cfg->dims[k];
+  h->NY = ny;
+  h->tau = cfg->tau;
+  h->prec = cfg->precision == ST_BF16X3 ? Prec::BF16X3 : Prec::FP32;
+  h->orth_tol = cfg->orth_tol > 0.0 ? cfg->orth_tol : 1e-5;
+  h->guard_rel = cfg->guard_rel > 0.0 ? cfg->guard_rel : (h->prec == Prec::BF16X3 ? 0.1 : 0.0);
+  h->max_rank_d = cfg->max_rank_d;
+  h->profile = cfg->profile != 0;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) {
+    if (cfg->stream) {
+      h->stream = (hipStream_t)cfg->stream;
+    } else {
+      e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+      h->own_stream = (e == hipSuccess);
+    }
+  }
+  for (int k = 0; k < h->m && e == hipSuccess; ++k) {
+    const int64_t nk = h->n[k];
+    h->ldb[k] = round_up(nk, 8);
+    e = hipMalloc((void **)&h->U64[k], nk * nk * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->Uf[k], nk * nk * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->Ut[k], nk * nk * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->Uh[k], nk * h->ldb[k] * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->Ul[k], nk * h->ldb[k] * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMemsetAsync(h->Ut[k], 0, nk * nk * sizeof(float), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->Uf[k], 0, nk * nk * sizeof(float), h->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(h->Uh[k], 0, nk * h->ldb[k] * sizeof(__bf16), h->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(h->Ul[k], 0, nk * h->ldb[k] * sizeof(__bf16), h->stream);
+  }
+  if (e == hipSuccess) e = h->D[0].ensure(ny);
+  if (e == hipSuccess) e = h->D[1].ensure(ny);
+  if (e == hipSuccess) e = h->sums.ensure(64);
+  if (e == hipSuccess) e = h->ensure_pinned(1024);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    g_create_error = std::string("device setup failed: ") + hipGetErrorString(e);
+    h->destroy();
+    delete h;
+    return e == hipErrorOutOfMemory ? ST_ENOMEM : ST_EHIP;
+  }
+  if (rocblas_create_handle(&h->rb) != rocblas_status_success ||
+      rocblas_set_stream(h->rb, h->stream) != rocblas_status_success) {
+    g_create_error = "rocblas handle setup failed";
+    h->destroy();
+    delete h;
+    return ST_EHIP;
+  }
+  *out = h;
+  return ST_OK;
+}
+
+int st_init(st_handle *h, const float *x0, int64_t n_init) {
+  if (!h) return ST_EINVAL;
+  (void)hipSetDevice(h->device);
+  return h->do_init(x0, n_init);
+}
+
+int st_update(st_handle *h, const float *y) {
+  if (!h) return ST_EINVAL;
+  (void)hipSetDevice(h->device);
+  return h->do_update(y);
+}
+
+int st_ranks(const st_handle *h, int64_t *ranks, int64_t *n_d) {
+  if (!h || !ranks) return ST_EINVAL;
+  for (int k = 0; k < h->m; ++k) ranks[k] = h->r[k];
+  ranks[h->m] = h->rd;
+  if (n_d) *n_d = h->nd;
+  return ST_OK;
+}
+
+int st_core(const st_handle *hc, float *out, int64_t cap, int64_t *need, int where) {
+  st_handle *h = const_cast<st_handle *>(hc);
+  if (!h) return ST_EINVAL;
+  if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
+  const int64_t cnt = h->rprod(h->r, h->m) * h->rd;
+  if (need) *need = cnt;
+  if (!out) return ST_OK;
+  if (cap < cnt) return h->fail(ST_ESMALL, "core buffer too small");
+  (void)hipSetDevice(h->device);
+  hipError_t e = hipMemcpyAsync(out, h->C[h->cur].p, cnt * sizeof(float),
+                                where == ST_DEVICE ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hipfail(e, "core copy");
+  return ST_OK;
+}
+
+int st_factor(const st_handle *hc, int mode, double *out, int64_t cap, int64_t *rows,
+              int64_t *cols, int where) {
+  st_handle *h = const_cast<st_handle *>(hc);
+  if (!h) return ST_EINVAL;
+  if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
+  if (mode < 0 || mode > h->m) return h->fail(ST_EINVAL, "mode out of range");
+  const int64_t nr = (mode < h->m) ? h->n[mode] : h->nd;
+  const int64_t nc = (mode < h->m) ? h->r[mode] : h->rd;
+  if (rows) *rows = nr;
+  if (cols) *cols = nc;
+  if (!out) return ST_OK;
+  if (cap < nr * nc) return h->fail(ST_ESMALL, "factor buffer too small");
+  (void)hipSetDevice(h->device);
+  const hipMemcpyKind kind = where == ST_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  hipError_t e;
+  if (mode < h->m) {
+    e = hipMemcpyAsync(out, h->U64[mode], nr * nc * sizeof(double), kind, h->stream);
+  } else {
+    e = hipMemcpy2DAsync(out, nr * sizeof(double), h->Ud[h->cur].p,
+                         h->ud_ld[h->cur] * sizeof(double), nr * sizeof(double), nc, kind,
+                         h->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hipfail(e, "factor copy");
+  return ST_OK;
+}
+
+int st_sv(const st_handle *h, double *s, int64_t cap, int64_t *count) {
+  if (!h) return ST_EINVAL;
+  if (count) *count = (int64_t)h->S_host.size();
+  if (!s) return ST_OK;
+  if (cap < (int64_t)h->S_host.size()) return ST_ESMALL;
+  std::copy(h->S_host.begin(), h->S_host.end(), s);
+  return ST_OK;
+}
+
+int st_recon_error(const st_handle *h, double *rel_bound, double *norm_x) {
+  if (!h) return ST_EINVAL;
+  if (!h->inited) return ST_ESTATE;
+  if (rel_bound) *rel_bound = h->xnorm2 > 0 ? std::sqrt(h->disc / h->xnorm2) : 0.0;
+  if (norm_x) *norm_x = std::sqrt(h->xnorm2);
+  return ST_OK;
+}
+
+int st_stats(const st_handle *h, st_slice_stats *out) {
+  if (!h || !out) return ST_EINVAL;
+  *out = h->stats;
+  return ST_OK;
+}
+
+int st_reconstruct_slice(const st_handle *hc, int64_t t, float *out) {
+  st_handle *h = const_cast<st_handle *>(hc);
+  if (!h) return ST_EINVAL;
+  (void)hipSetDevice(h->device);
+  return h->do_reconstruct_slice(t, out);
+}
+
+int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
+           int64_t rows, float *out, double *norms, int32_t precision, void *stream) {
+  if (!x || !dims || !a || !out || nmodes < 1 || nmodes > ST_MAX_MODES || mode < 0 ||
+      mode >= nmodes || rows < 1 || (precision != ST_FP32 && precision != ST_BF16X3))
+    return ST_EINVAL;
+  int64_t lo = 1, hi = 1;
+  for (int k = 0; k < nmodes; ++k) {
+    if (dims[k] < 1) return ST_EINVAL;
+    if (k < mode) lo *= dims[k];
+    if (k > mode) hi *= dims[k];
+  }
+  if (norms && rows > 256) return ST_EINVAL;
+  const int64_t nk = dims[mode];
+  hipStream_t s = (hipStream_t)stream;
+  FiberIn in{};
+  in.x = x;
+  in.a = lo;
+  in.n = nk;
+  in.F = lo * hi;
+  FiberW w{};
+  w.w = a;
+  w.ldw = nk;
+  __bf16 *bh = nullptr, *bl = nullptr;
+  double *part = nullptr, *sum = nullptr;
+  const Prec pr = precision == ST_BF16X3 ? Prec::BF16X3 : Prec::FP32;
+  hipError_t e = hipSuccess;
+  if (pr == Prec::BF16X3) {
+    const int64_t ldb = round_up(nk, 8);
+    e = hipMalloc((void **)&bh, rows * ldb * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMalloc((void **)&bl, rows * ldb * sizeof(__bf16));
+    if (e == hipSuccess) e = launch_split_rows(a, rows, nk, nk, bh, bl, ldb, s);
+    w.w_hi = bh;
+    w.w_lo = bl;
+    w.ldw_bf = ldb;
+  }
+  const int nb = st_handle::fiber_nblocks(in.F);
+  if (e == hipSuccess && norms) {
+    e = hipMalloc((void **)&part, 2 * (size_t)nb * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&sum, 2 * sizeof(double));
+  }
+  if (e == hipSuccess)
+    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, lo, rows}, part, pr, s);
+  if (e == hipSuccess && norms) e = launch_reduce_pairs(part, nb, sum, s);
+  if (e == hipSuccess && norms)
+    e = hipMemcpyAsync(norms, sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (bh) (void)hipFree(bh);
+  if (bl) (void)hipFree(bl);
+  if (part) (void)hipFree(part);
+  if (sum) (void)hipFree(sum);
+  if (e == hipErrorOutOfMemory) return ST_ENOMEM;
+  return e == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
+            int64_t rows, double *g, int32_t gram_precision, void *stream) {
+  if (!x || !dims || !g || nmodes < 1 || nmodes > ST_MAX_MODES || mode < 0 || mode >= nmodes ||
+      rows < 0 || rows > 256 || (rows > 0 && !a) || gram_precision < 0 || gram_precision > 2)
+    return ST_EINVAL;
+  int64_t lo = 1, hi = 1;
+  for (int k = 0; k < nmodes; ++k) {
+    if (dims[k] < 1) return ST_EINVAL;
+    if (k < mode) lo *= dims[k];
+    if (k > mode) hi *= dims[k];
+  }
+  const int64_t nk = dims[mode];
+  if (nk > 512 || rows > nk) return ST_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  FiberIn in{};
+  in.x = x;
+  in.a = lo;
+  in.n = nk;
+  in.F = lo * hi;
+  FiberW w{};
+  w.w = a;
+  w.ldw = nk;
+  const int nb = gram_blocks(in.F);
+  double *part = nullptr, *G = nullptr;
+  hipError_t e = hipMalloc((void **)&part, gram_partial_elems(nk, nb) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&G, nk * nk * sizeof(double));
+  if (e == hipSuccess) e = launch_gram(in, w, (int)rows, part, nb, (GramPrec)gram_precision, s);
+  if (e == hipSuccess) e = launch_gram_reduce(part, nb, nk, G, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g, G, nk * nk * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (part) (void)hipFree(part);
+  if (G) (void)hipFree(G);
+  if (e == hipErrorOutOfMemory) return ST_ENOMEM;
+  return e == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_profile(st_handle *h, st_kernel_profile *out, int32_t count, int32_t reset) {
+  if (!h || (out == nullptr && count > 0) || count < 0) return ST_EINVAL;
+  for (int i = 0; i < count && i < ST_K_GROUPS; ++i) out[i] = h->prof[i];
+  if (reset)
+    for (int i = 0; i < ST_K_GROUPS; ++i) h->prof[i] = st_kernel_profile{};
+  return ST_OK;
+}
+
+void st_destroy(st_handle *h) {
+  if (!h) return;
+  h->destroy();
+  delete h;
+}
+
+const char *st_last_error(const st_handle *h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,527 @@
+// Streaming-mode kernels (Alg. 3 and the core update of Alg. 5) plus small
+// FP64 helpers for the non-streaming factor growth (Alg. 4 with Alg. 1).
+#include "common.hpp"
+#include "kernels.hpp"
+#include "secular.hpp"
+
+namespace st {
+
+// ---------------------------------------------------------------------------
+// CGS2 passes over V (Alg. 3, first lines, with a second Gram-Schmidt pass).
+//
+// V is the old auxiliary matrix (rows at the old ranks, leading dimension ldv,
+// r columns); d, e are vectors at the new ranks; rows are mapped new -> old.
+// Each block stages a tile of TR rows x r columns of V in LDS with coalesced
+// loads, then
+//   PASS 1: colpart += V^T d
+//   PASS 2: e1 = d - V p1 (row dots), colpart += V^T e1
+//   PASS 3: e = (d - V p1) - V p2, store e, q2 += e^2, colpart += V^T e
+// so that V is read from HBM once per pass.
+// ---------------------------------------------------------------------------
+template <int PASS>
+__global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
+  extern __shared__ double sh[];
+  const int TR = a.tile_rows;
+  const int r = a.r;
+  const int tid = threadIdx.x;
+  double *p1s = sh;                    // [r]
+  double *p2s = p1s + r;               // [r]
+  double *ev = p2s + r;                // [TR]
+  double *rowred = ev + TR;            // [256] = [threads per row][TR]
+  int64_t *orow = reinterpret_cast<int64_t *>(rowred + 256);     // [TR]
+  float *tile = reinterpret_cast<float *>(orow + TR);            // [r][TR+1]
+  const int ldt = TR + 1;
+
+  if (PASS >= 2)
+    for (int j = tid; j < r; j += blockDim.x) p1s[j] = a.p1[j];
+  if (PASS >= 3)
+    for (int j = tid; j < r; j += blockDim.x) p2s[j] = a.p2[j];
+
+  constexpr int kMaxCols = 8;  // r <= 2048
+  double colacc[kMaxCols];
+#pragma unroll
+  for (int q = 0; q < kMaxCols; ++q) colacc[q] = 0.0;
+  double q2 = 0.0;
+
+  const int64_t ntiles = (a.R + TR - 1) / TR;
+  const int tpr = blockDim.x / TR;  // threads per row in the row phase
+  for (int64_t tile_i = blockIdx.x; tile_i < ntiles; tile_i += gridDim.x) {
+    const int64_t row0 = tile_i * TR;
+    __syncthreads();
+    if (tid < TR) {
+      const int64_t row = row0 + tid;
+      orow[tid] = row < a.R ? map_new_to_old(a.map, row) : -1;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < r * TR; idx += blockDim.x) {
+      const int j = idx / TR, i = idx - j * TR;
+      const int64_t o = orow[i];
+      tile[j * ldt + i] = (o >= 0) ? a.V[o + a.ldv * (int64_t)j] : 0.0f;
+    }
+    __syncthreads();
+    // row phase
+    if (PASS == 1) {
+      if (tid < TR) {
+        const int64_t row = row0 + tid;
+        ev[tid] = row < a.R ? (double)a.d[row] : 0.0;
+      }
+    } else {
+      const int i = tid % TR, sub = tid / TR;
+      double s1 = 0.0, s2 = 0.0;
+      if (sub < tpr) {
+        for (int j = sub; j < r; j += tpr) {
+          const double vj = (double)tile[j * ldt + i];
+          s1 += vj * p1s[j];
+          if (PASS == 3) s2 += vj * p2s[j];
+        }
+      }
+      if (sub < tpr) rowred[sub * TR + i] = s1;
+      __syncthreads();
+      if (tid < TR) {
+        double t1 = 0.0;
+        for (int q = 0; q < tpr; ++q) t1 += rowred[q * TR + tid];
+        rowred[tid] = t1;  // reuse slot 0 after everyone summed (see sync below)
+      }
+      __syncthreads();
+      double dot1 = (tid < TR) ? rowred[tid] : 0.0;
+      __syncthreads();
+      if (PASS == 3) {
+        if (sub < tpr) rowred[sub * TR + i] = s2;
+        __syncthreads();
+        if (tid < TR) {
+          double t2 = 0.0;
+          for (int q = 0; q < tpr; ++q) t2 += rowred[q * TR + tid];
+          rowred[tid] = t2;
+        }
+        __syncthreads();
+      }
+      if (tid < TR) {
+        const int64_t row = row0 + tid;
+        double val = 0.0;
+        if (row < a.R) {
+          const double e1 = (double)a.d[row] - dot1;
+          if (PASS == 2) {
+            val = e1;
+          } else {
+            val = e1 - rowred[tid];
+            a.e[row] = (float)val;
+            q2 += val * val;
+          }
+        }
+        ev[tid] = val;
+      }
+    }
+    __syncthreads();
+    // column phase
+#pragma unroll
+    for (int q = 0; q < kMaxCols; ++q) {
+      const int j = tid + q * blockDim.x;
+      if (j < r) {
+        double s = 0.0;
+        const float *tr = tile + j * ldt;
+        for (int i = 0; i < TR; ++i) s += (double)tr[i] * ev[i];
+        colacc[q] += s;
+      }
+    }
+  }
+  double *dst = a.colpart + (size_t)blockIdx.x * r;
+#pragma unroll
+  for (int q = 0; q < kMaxCols; ++q) {
+    const int j = tid + q * blockDim.x;
+    if (j < r) dst[j] = colacc[q];
+  }
+  if (PASS == 3) {
+    __shared__ double red[16];
+    const double t = block_sum(q2, red);
+    if (tid == 0) a.q2part[blockIdx.x] = t;
+  }
+}
+
+// out[j] = sum_b part[b * r + j] (fixed order); optionally out2[j] = out[j] + add[j];
+// optionally q2 = sum_b q2part[b].
+__global__ void colsum_kernel(const double *part, int nb, int r, double *out, const double *add,
+                              double *out2, const double *q2part, double *q2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < r) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * r + j];
+    out[j] = s;
+    if (out2) out2[j] = s + add[j];
+  }
+  if (q2part && blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += q2part[b];
+    q2[0] = s;
+  }
+}
+
+int isvd_blocks(int64_t R) {
+  const int64_t t = (R + 31) / 32;
+  return (int)(t < 1024 ? (t > 0 ? t : 1) : 1024);
+}
+
+static size_t isvd_lds(int r, int TR) {
+  return sizeof(double) * (2 * (size_t)r + TR + 256) + sizeof(int64_t) * TR +
+         sizeof(float) * (size_t)r * (TR + 1);
+}
+
+hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s) {
+  if (a.r > 8 * 256) return hipErrorInvalidValue;
+  int TR = 32;
+  while (TR > 4 && isvd_lds(a.r, TR) > 150 * 1024) TR /= 2;
+  a.tile_rows = TR;
+  const size_t lds = isvd_lds(a.r, TR);
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  if (pass == 1) {
+    hipFuncSetAttribute((const void *)isvd_pass_kernel<1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(isvd_pass_kernel<1>, dim3(nblocks), dim3(256), lds, s, a);
+  } else if (pass == 2) {
+    hipFuncSetAttribute((const void *)isvd_pass_kernel<2>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(isvd_pass_kernel<2>, dim3(nblocks), dim3(256), lds, s, a);
+  } else {
+    hipFuncSetAttribute((const void *)isvd_pass_kernel<3>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(isvd_pass_kernel<3>, dim3(nblocks), dim3(256), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const double *part, int nb, int r, double *out, const double *add,
+                         double *out2, const double *q2part, double *q2, hipStream_t s) {
+  const int blocks = (r + 255) / 256 > 0 ? (r + 255) / 256 : 1;
+  hipLaunchKernelGGL(colsum_kernel, dim3(blocks), dim3(256), 0, s, part, nb, r, out, add, out2,
+                     q2part, q2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Secular-equation SVD of S' (see secular.hpp).
+// ---------------------------------------------------------------------------
+struct WaveRed {
+  int lane;
+  template <class F>
+  __device__ double sum(int m, F f) const {
+    double acc = 0.0;
+    for (int j = lane; j < m; j += kWave) acc += f(j);
+    return wave_sum(acc);
+  }
+  template <class F>
+  __device__ double prod(int m, F f) const {
+    double acc = 1.0;
+    for (int j = lane; j < m; j += kWave) acc *= f(j);
+    return wave_prod(acc);
+  }
+  template <class F>
+  __device__ void for_each(int m, F f) const {
+    for (int j = lane; j < m; j += kWave) f(j);
+  }
+  __device__ void sync() const { __syncthreads(); }
+  template <class F>
+  __device__ void single(F f) const {
+    if (lane == 0) f();
+  }
+};
+
+__global__ void sec_prep_kernel(SecData s, const double *S, const double *p, double q, int grow,
+                                double tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sec_prep(s, S, p, q, grow, tol);
+}
+
+__global__ __launch_bounds__(256) void sec_roots_kernel(SecData s) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= s.counts[0]) return;
+  WaveRed red{(int)(threadIdx.x & 63)};
+  int o;
+  double mu;
+  sec_root(s, i, red, &o, &mu);
+  if ((threadIdx.x & 63) == 0) {
+    s.org[i] = o;
+    s.mu[i] = mu;
+  }
+}
+
+__global__ __launch_bounds__(256) void sec_zhat_kernel(SecData s) {
+  const int jt = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int m = s.counts[0];
+  const int lane = threadIdx.x & 63;
+  if (jt >= s.n) return;
+  if (jt >= m) return;
+  WaveRed red{lane};
+  const double z = sec_zhat(s, jt, red);
+  if (lane == 0) s.zh[s.K[jt]] = z;
+}
+
+__global__ void sec_zero_zh_kernel(SecData s) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < s.n) s.zh[t] = 0.0;
+}
+
+// One wave (block of 64) per output triplet. U2 and V2 are (r+1) x ntrip,
+// column-major with leading dimension r+1, in the original index order of S'.
+__global__ __launch_bounds__(64) void sec_vec_kernel(SecData s, int ntrip, double *U2, double *V2,
+                                                     double *Snew) {
+  extern __shared__ double vs[];
+  double *u = vs, *v = vs + s.n;
+  const int trip = blockIdx.x;
+  const int lane = threadIdx.x;
+  WaveRed red{lane};
+  double nu, nv;
+  const double sigma = sec_vectors(s, trip, u, v, red, &nu, &nv);
+  const int col = sec_rank(s, trip, ntrip, red);
+  const int r = s.r, ld = r + 1;
+  const double iu = nu > 0.0 ? 1.0 / nu : 0.0, iv = nv > 0.0 ? 1.0 / nv : 0.0;
+  for (int t = lane; t < s.n; t += kWave) {
+    const int orig = (t == 0) ? r : r - t;
+    U2[orig + (size_t)ld * col] = u[t] * iu;
+    V2[orig + (size_t)ld * col] = v[t] * iv;
+  }
+  if (lane == 0) Snew[col] = sigma;
+}
+
+hipError_t launch_secular_svd(SecData s, const double *S, const double *p, double q, int grow,
+                              double tol, int ntrip, double *U2, double *V2, double *Snew,
+                              hipStream_t st) {
+  const int n = s.n;
+  hipLaunchKernelGGL(sec_zero_zh_kernel, dim3((n + 255) / 256), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(sec_prep_kernel, dim3(1), dim3(64), 0, st, s, S, p, q, grow, tol);
+  hipLaunchKernelGGL(sec_roots_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(sec_zhat_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
+  const size_t lds = 2 * (size_t)n * sizeof(double);
+  if (lds > 64 * 1024)
+    hipFuncSetAttribute((const void *)sec_vec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  hipLaunchKernelGGL(sec_vec_kernel, dim3(ntrip), dim3(64), lds, st, s, ntrip, U2, V2, Snew);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// U~_d = [U_d U''(0:r, :); U''(r, :)] (Alg. 3, left factor without forming U').
+// ---------------------------------------------------------------------------
+__global__ void ud_update_kernel(const double *Ud, int64_t ldo, int64_t nd, int r, const double *U2,
+                                 int c, double *Un, int64_t ldn) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (nd + 1) * c;
+  if (idx >= total) return;
+  const int64_t row = idx % (nd + 1);
+  const int col = (int)(idx / (nd + 1));
+  const double *u2c = U2 + (size_t)(r + 1) * col;
+  double s;
+  if (row < nd) {
+    s = 0.0;
+    for (int k = 0; k < r; ++k) s += Ud[row + ldo * k] * u2c[k];
+  } else {
+    s = u2c[r];
+  }
+  Un[row + ldn * col] = s;
+}
+
+hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, const double *U2,
+                            int c, double *Un, int64_t ldn, hipStream_t s) {
+  const int64_t total = (nd + 1) * c;
+  hipLaunchKernelGGL(ud_update_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Ud,
+                     ldo, nd, r, U2, c, Un, ldn);
+  return hipGetLastError();
+}
+
+// Row-major FP32 rotation matrices for the mode-d TTMs of V and C:
+//   Wv[m][k] = V''[k][m] (k < kv), with row r scaled by 1/q when e is kept;
+//   Wc[m][k] = U''[k][m] (k <= r).
+__global__ void build_rot_w_kernel(const double *U2, const double *V2, int r, int c, int kv,
+                                   double inv_q, float *Wv, int64_t ldv, float *Wc, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)c * (r + 1);
+  if (idx >= total) return;
+  const int m = (int)(idx / (r + 1)), k = (int)(idx % (r + 1));
+  const size_t src = (size_t)k + (size_t)(r + 1) * m;
+  Wc[m * ldc + k] = (float)U2[src];
+  if (k < kv) Wv[m * ldv + k] = (float)(k == r ? V2[src] * inv_q : V2[src]);
+}
+
+hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
+                              double inv_q, float *Wv, int64_t ldv, float *Wc, int64_t ldc,
+                              hipStream_t s) {
+  const int64_t total = (int64_t)c * (r + 1);
+  hipLaunchKernelGGL(build_rot_w_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     U2, V2, r, c, kv, inv_q, Wv, ldv, Wc, ldc);
+  return hipGetLastError();
+}
+
+// Init: Wv[m][j] = U_d[j][m] / S[m], Wc[m][j] = U_d[j][m] (row-major, j < nd).
+__global__ void build_init_w_kernel(const double *Ud, int64_t ldu, int64_t nd, int rd,
+                                    const double *S, float *Wv, float *Wc, int64_t ldw) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nd * rd) return;
+  const int m = (int)(idx / nd);
+  const int64_t j = idx % nd;
+  const double u = Ud[j + ldu * m];
+  Wc[m * ldw + j] = (float)u;
+  Wv[m * ldw + j] = (float)(u / S[m]);
+}
+
+hipError_t launch_build_init_w(const double *Ud, int64_t ldu, int64_t nd, int rd, const double *S,
+                               float *Wv, float *Wc, int64_t ldw, hipStream_t s) {
+  const int64_t total = nd * rd;
+  hipLaunchKernelGGL(build_init_w_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     Ud, ldu, nd, rd, S, Wv, Wc, ldw);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Factor growth helpers (FP64).
+// ---------------------------------------------------------------------------
+// W[:, c] = Q[:, n-1-c] for c < k (eigenvectors in descending eigenvalue order).
+__global__ void take_top_kernel(const double *Q, int64_t n, int k, double *W) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int c = (int)(idx / n);
+  const int64_t i = idx % n;
+  W[i + n * c] = Q[i + n * (n - 1 - c)];
+}
+
+// coef[j + r*c] = U(:,j)^T W(:,c)
+__global__ void proj_coef_kernel(const double *U, int64_t n, int r, const double *W, int k,
+                                 double *coef) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= r * k) return;
+  const int j = idx % r, c = idx / r;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += U[i + n * j] * W[i + n * c];
+  coef[idx] = s;
+}
+
+// W(i, c) -= sum_j U(i, j) coef[j + r*c]
+__global__ void proj_sub_kernel(const double *U, int64_t n, int r, double *W, int k,
+                                const double *coef) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx % n;
+  const int c = (int)(idx / n);
+  double s = 0.0;
+  for (int j = 0; j < r; ++j) s += U[i + n * j] * coef[j + r * c];
+  W[i + n * c] -= s;
+}
+
+// Modified Gram-Schmidt among the k columns of W, then normalisation.
+__global__ void mgs_kernel(double *W, int64_t n, int k) {
+  __shared__ double red[16];
+  for (int c = 0; c < k; ++c) {
+    double *wc = W + n * c;
+    for (int p = 0; p < c; ++p) {
+      const double *wp = W + n * p;
+      double s = 0.0;
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += wp[i] * wc[i];
+      s = block_sum(s, red);
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) wc[i] -= s * wp[i];
+      __syncthreads();
+    }
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += wc[i] * wc[i];
+    s = block_sum(s, red);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) wc[i] *= inv;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_new_columns(const double *Q, int64_t n, const double *U, int r, int k,
+                              double *W, double *coef, hipStream_t s) {
+  const int64_t nk = n * k;
+  hipLaunchKernelGGL(take_top_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, Q, n, k,
+                     W);
+  if (r > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(proj_coef_kernel, dim3((r * k + 255) / 256), dim3(256), 0, s, U, n, r, W,
+                         k, coef);
+      hipLaunchKernelGGL(proj_sub_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, U,
+                         n, r, W, k, coef);
+    }
+  }
+  hipLaunchKernelGGL(mgs_kernel, dim3(1), dim3(256), 0, s, W, n, k);
+  return hipGetLastError();
+}
+
+// Write columns [c0, c0 + k) of U_k from W (n x k, FP64) into the FP64 master
+// (col-major, ld n), the FP32 copy Uf (col-major = row-major U^T, ld n), the
+// row-major FP32 Ut (ld n) and the bf16 splits of Uf (row-major U^T, ld ldb).
+__global__ void append_cols_kernel(const double *W, int64_t n, int c0, int k, double *U64,
+                                   float *Uf, float *Ut, __bf16 *Uh, __bf16 *Ul, int64_t ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx % n;
+  const int c = (int)(idx / n);
+  const double w = W[i + n * c];
+  const int64_t col = c0 + c;
+  U64[i + n * col] = w;
+  const float f = (float)w;
+  Uf[i + n * col] = f;
+  Ut[i * n + col] = f;
+  const __bf16 h = (__bf16)f;
+  Uh[col * ldb + i] = h;
+  Ul[col * ldb + i] = (__bf16)(f - (float)h);
+}
+
+hipError_t launch_append_cols(const double *W, int64_t n, int c0, int k, double *U64, float *Uf,
+                              float *Ut, __bf16 *Uh, __bf16 *Ul, int64_t ldb, hipStream_t s) {
+  const int64_t nk = n * k;
+  hipLaunchKernelGGL(append_cols_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, W, n,
+                     c0, k, U64, Uf, Ut, Uh, Ul, ldb);
+  return hipGetLastError();
+}
+
+// Per-block FP64 sum of squares (pairs layout: {sum, 0}).
+__global__ void sumsq_kernel(const float *x, int64_t count, double *partials) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)x[i];
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s;
+    partials[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+hipError_t launch_sumsq(const float *x, int64_t count, double *partials, int nblocks,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nblocks), dim3(256), 0, s, x, count, partials);
+  return hipGetLastError();
+}
+
+// FP64 -> FP32 row of U_d for slice reconstruction: w[m] = U_d[t + ld*m].
+__global__ void ud_row_kernel(const double *Ud, int64_t ld, int64_t t, int rd, float *w) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < rd) w[m] = (float)Ud[t + ld * m];
+}
+
+hipError_t launch_ud_row(const double *Ud, int64_t ld, int64_t t, int rd, float *w,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(ud_row_kernel, dim3((rd + 255) / 256), dim3(256), 0, s, Ud, ld, t, rd, w);
+  return hipGetLastError();
+}
+
+// bf16 split of a row-major FP32 matrix: hi = bf16(w), lo = bf16(w - hi).
+__global__ void split_rows_kernel(const float *w, int64_t rows, int64_t n, int64_t ldw,
+                                  __bf16 *hi, __bf16 *lo, int64_t ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ldb) return;
+  const int64_t i = idx / ldb, j = idx % ldb;
+  const float f = j < n ? w[i * ldw + j] : 0.0f;
+  const __bf16 h = (__bf16)f;
+  hi[idx] = h;
+  lo[idx] = (__bf16)(f - (float)h);
+}
+
+hipError_t launch_split_rows(const float *w, int64_t rows, int64_t n, int64_t ldw, __bf16 *hi,
+                             __bf16 *lo, int64_t ldb, hipStream_t s) {
+  const int64_t total = rows * ldb;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w,
+                     rows, n, ldw, hi, lo, ldb);
+  return hipGetLastError();
+}
+
+}  // namespace st

@@ -1,0 +1,50 @@
+// Launchers of the streaming-mode and helper kernels (k_isvd.hip).
+#pragma once
+
+#include "common.hpp"
+#include "secular.hpp"
+
+namespace st {
+
+struct IsvdArgs {
+  const float *V;      // old V (or any old mode-d matrix), column-major
+  int64_t ldv;         // its leading dimension (old row count)
+  int r;               // columns
+  int64_t R;           // rows at the new ranks
+  RowMap map;          // new row -> old row
+  const float *d;      // [R] new slice projection
+  const double *p1;    // [r]
+  const double *p2;    // [r]
+  float *e;            // [R] output of pass 3
+  double *colpart;     // [nblocks * r]
+  double *q2part;      // [nblocks]
+  int tile_rows;       // set by the launcher
+};
+
+int isvd_blocks(int64_t R);
+hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s);
+hipError_t launch_colsum(const double *part, int nb, int r, double *out, const double *add,
+                         double *out2, const double *q2part, double *q2, hipStream_t s);
+hipError_t launch_secular_svd(SecData s, const double *S, const double *p, double q, int grow,
+                              double tol, int ntrip, double *U2, double *V2, double *Snew,
+                              hipStream_t st);
+hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, const double *U2,
+                            int c, double *Un, int64_t ldn, hipStream_t s);
+hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
+                              double inv_q, float *Wv, int64_t ldv, float *Wc, int64_t ldc,
+                              hipStream_t s);
+hipError_t launch_build_init_w(const double *Ud, int64_t ldu, int64_t nd, int rd, const double *S,
+                               float *Wv, float *Wc, int64_t ldw, hipStream_t s);
+hipError_t launch_new_columns(const double *Q, int64_t n, const double *U, int r, int k,
+                              double *W, double *coef, hipStream_t s);
+hipError_t launch_append_cols(const double *W, int64_t n, int c0, int k, double *U64, float *Uf,
+                              float *Ut, __bf16 *Uh, __bf16 *Ul, int64_t ldb, hipStream_t s);
+hipError_t launch_sumsq(const float *x, int64_t count, double *partials, int nblocks,
+                        hipStream_t s);
+hipError_t launch_ud_row(const double *Ud, int64_t ld, int64_t t, int rd, float *w,
+                         hipStream_t s);
+
+hipError_t launch_split_rows(const float *w, int64_t rows, int64_t n, int64_t ldw, __bf16 *hi,
+                             __bf16 *lo, int64_t ldb, hipStream_t s);
+
+}  // namespace st

@@ -1,0 +1,98 @@
+"""GPU: the mode-k TTM kernel (st_ttm) against numpy, FP32 and bf16x3.
+
+Covers contiguous (mode 1) and strided fibres, ragged sizes that are not
+multiples of the 16 x 32 MFMA tiles, one and several output-row tiles, and the
+fused residual norm ||X - (X x_k U^T) x_k U||^2 with ||X||^2.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(dims, mode, rows, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(dims).astype(np.float32)
+    u, _ = np.linalg.qr(rng.standard_normal((dims[mode], rows)))
+    return x, u.astype(np.float32)
+
+
+def _ref(x, a, mode):
+    x64 = x.astype(np.float64)
+    a64 = a.astype(np.float64)
+    y = np.moveaxis(np.tensordot(a64, x64, axes=([1], [mode])), 0, mode)
+    back = np.moveaxis(np.tensordot(a64.T, y, axes=([1], [mode])), 0, mode)
+    return y, np.sum((x64 - back) ** 2), np.sum(x64 ** 2)
+
+
+CASES = [
+    ((128, 64, 3), 0, 33),
+    ((32, 40, 7), 1, 5),
+    ((20, 37, 9, 3), 2, 9),
+    ((16, 16, 16, 16), 3, 16),
+    ((33, 17, 5), 0, 1),
+    ((64, 48, 5), 1, 48),
+    ((200, 30), 0, 130),
+    ((12, 300), 1, 260),
+]
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("dims,mode,rows", CASES)
+def test_ttm_projection_and_residual(dims, mode, rows, precision, rtol):
+    import torch
+
+    from paper_2308_16395_amd.binding import ttm
+
+    rows = min(rows, dims[mode])
+    x, u = _case(dims, mode, rows, sum(dims) + rows)
+    # column-major device layout: the C-ordered array of the reversed axes
+    xd = torch.from_numpy(np.ascontiguousarray(x.ravel(order="F"))).cuda()
+    a = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()  # rows x n, row-major
+    want_norms = rows <= 256
+    res = ttm(xd, dims, mode, a, precision=precision, norms=want_norms)
+    out, norms = (res if want_norms else (res, None))
+    y_ref, e2_ref, x2_ref = _ref(x, u.T, mode)
+    out_dims = list(dims)
+    out_dims[mode] = rows
+    y = out.cpu().numpy().reshape(out_dims, order="F")
+    scale = np.abs(y_ref).max()
+    np.testing.assert_allclose(y, y_ref, rtol=0, atol=rtol * scale * np.sqrt(dims[mode]))
+    if want_norms:
+        e2, x2 = norms
+        np.testing.assert_allclose(x2, x2_ref, rtol=1e-12)
+        # the residual norm squared is accurate to the product precision relative to ||X||^2
+        assert abs(e2 - e2_ref) <= (1e-5 if precision == "fp32" else 1e-3) * x2_ref
+
+
+GRAM_CASES = [
+    ((32, 320), 0, 0),
+    ((128, 40, 3), 0, 33),
+    ((20, 37, 9, 3), 2, 0),
+    ((24, 17, 5), 1, 6),
+    ((9, 20), 1, 0),
+    ((260, 7), 0, 40),
+]
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-13), ("fp32", 1e-5), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("dims,mode,rows", GRAM_CASES)
+def test_gram_against_numpy(dims, mode, rows, precision, rtol):
+    import torch
+
+    from paper_2308_16395_amd.binding import gram
+
+    x, u = _case(dims, mode, max(rows, 1), sum(dims) + 7 * rows)
+    xd = torch.from_numpy(np.ascontiguousarray(x.ravel(order="F"))).cuda()
+    a = torch.from_numpy(np.ascontiguousarray(u.T)).cuda() if rows > 0 else None
+    g = gram(xd, dims, mode, a, precision=precision)
+    x64 = np.moveaxis(x.astype(np.float64), mode, 0).reshape(dims[mode], -1)
+    if rows > 0:
+        u64 = u.astype(np.float64)
+        x64 = x64 - u64 @ (u64.T @ x64)
+    ref = x64 @ x64.T
+    # the residual is formed in FP32, so its Gram is accurate to ~1e-6 of ||X||^2
+    tol = rtol * np.abs(ref).max() if rows == 0 else max(rtol * np.abs(ref).max(),
+                                                         1e-5 * np.sum(x.astype(np.float64) ** 2) / dims[mode])
+    np.testing.assert_allclose(g, ref, rtol=0, atol=tol)
