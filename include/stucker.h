@@ -47,8 +47,11 @@ enum st_status {
 };
 
 enum st_precision {
-  ST_FP32 = 0,   /* TTM chain and Gram products as FP32 MFMA, FP32 accumulation */
-  ST_BF16X3 = 1  /* the same products as split-BF16 (hi*hi + hi*lo + lo*hi) MFMA */
+  ST_FP32 = 0,    /* TTM chain and Gram products as FP32 MFMA, FP32 accumulation */
+  ST_BF16X3 = 1,  /* the same products as split-BF16 (hi*hi + hi*lo + lo*hi) MFMA */
+  ST_FP64 = 2     /* the same products on the FP64 MFMA: FP32 data and state, exact
+                     products, FP64 sums (the form that reproduces the FP64 rank
+                     decisions; see the header of st_update) */
 };
 
 enum st_where { ST_HOST = 0, ST_DEVICE = 1 };
@@ -59,8 +62,9 @@ typedef struct st_config {
   double tau;                  /* relative error tolerance (the paper's tau), > 0 */
   int32_t precision;           /* enum st_precision */
   double orth_tol;             /* eps_m of the ISVD orthogonality check; 0 = 1e-5 */
-  double guard_rel;            /* relative guard band around each threshold test in
-                                  which the test is re-evaluated in FP32; 0 = default */
+  double guard_rel;            /* relative guard band around each threshold test of
+                                  Alg. 4 in which ||E_k|| is re-evaluated with FP64
+                                  products; 0 = default (1e-2 FP32, 1e-1 bf16x3) */
   int64_t max_rank_d;          /* cap on the streaming rank r_d; 0 = no cap */
   void *stream;                /* hipStream_t to run on; NULL = library-owned stream */
   int32_t profile;             /* nonzero: time every kernel group with HIP events */
@@ -139,6 +143,12 @@ int st_ranks(const st_handle *h, int64_t *ranks, int64_t *n_d);
  * device pointer per `where`). out == NULL only sets *need (elements).
  * Errors: ST_ESMALL (cap < need; *need is set), ST_ESTATE, ST_EINVAL. */
 int st_core(const st_handle *h, float *out, int64_t cap, int64_t *need, int where);
+
+/* The auxiliary tensor V of the core factorization C = V x_d S (Sec. 3.2,
+ * Assumption 1(c)) as the column-major float32 matrix V_(d)^T of size
+ * (r_1 ... r_{d-1}) x r_d, into out (host or device). out == NULL only sets
+ * *need. Errors: ST_ESMALL, ST_ESTATE, ST_EINVAL. */
+int st_aux_v(const st_handle *h, float *out, int64_t cap, int64_t *need, int where);
 
 /* Dense factor U_mode (mode 0..d-1; mode d-1 is the streaming factor of size
  * n_d x r_d), column-major float64, into out (host or device). out == NULL only

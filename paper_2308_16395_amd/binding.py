@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libstucker.so")
 ST_MAX_MODES = 8
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EHIP, ST_ESTATE = 0, -1, -2, -3, -4
 ST_ENONFINITE, ST_EDEGENERATE, ST_ESMALL, ST_ECAPACITY, ST_ESOLVER = -5, -6, -7, -8, -9
-ST_FP32, ST_BF16X3 = 0, 1
+ST_FP32, ST_BF16X3, ST_FP64 = 0, 1, 2
+PRECISIONS = {"fp32": ST_FP32, "bf16x3": ST_BF16X3, "fp64": ST_FP64}
 ST_HOST, ST_DEVICE = 0, 1
 
 STATUS_NAMES = {
@@ -31,7 +32,7 @@ STATUS_NAMES = {
 
 EXPORTED = ["st_create", "st_init", "st_update", "st_ranks", "st_core", "st_factor",
             "st_sv", "st_recon_error", "st_stats", "st_reconstruct_slice",
-            "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile"]
+            "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile", "st_aux_v"]
 
 KERNEL_GROUPS = ["ttm1", "ttm", "gram", "eig", "ttm_ext", "isvd", "svd", "rot_v", "rot_c",
                  "ud"]
@@ -90,6 +91,7 @@ _sig = {
     "st_update": (C.c_int, [_h, C.c_void_p]),
     "st_ranks": (C.c_int, [_h, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "st_core": (C.c_int, [_h, C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_int]),
+    "st_aux_v": (C.c_int, [_h, C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_int]),
     "st_factor": (C.c_int, [_h, C.c_int, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64), C.c_int]),
     "st_sv": (C.c_int, [_h, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]),
@@ -115,6 +117,7 @@ st_update = lib.st_update
 st_ranks = lib.st_ranks
 st_core = lib.st_core
 st_factor = lib.st_factor
+st_aux_v = lib.st_aux_v
 st_sv = lib.st_sv
 st_recon_error = lib.st_recon_error
 st_stats = lib.st_stats
@@ -148,7 +151,7 @@ def ttm(x, dims, mode, a, precision="fp32", norms=False, stream=None):
         stream = torch.cuda.current_stream()
     rc = st_ttm(C.c_void_p(x.data_ptr()), len(dims), cdims, int(mode), C.c_void_p(a.data_ptr()),
                 rows, C.c_void_p(out.data_ptr()), nrm,
-                {"fp32": ST_FP32, "bf16x3": ST_BF16X3}[precision], C.c_void_p(stream.cuda_stream))
+                PRECISIONS[precision], C.c_void_p(stream.cuda_stream))
     if rc != ST_OK:
         raise StError(rc, "st_ttm failed")
     if norms:
@@ -199,7 +202,7 @@ class StreamingTucker:
         for k, n in enumerate(self.dims):
             cfg.dims[k] = n
         cfg.tau = float(tau)
-        cfg.precision = {"fp32": ST_FP32, "bf16x3": ST_BF16X3}[precision]
+        cfg.precision = PRECISIONS[precision]
         cfg.orth_tol = float(orth_tol)
         cfg.guard_rel = float(guard_rel)
         cfg.max_rank_d = int(max_rank_d)
@@ -266,6 +269,16 @@ class StreamingTucker:
         out = t.empty(need.value, dtype=t.float32, device="cuda")
         self._check(st_core(self._h, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE))
         return out
+
+    def aux_v(self):
+        """V of C = V x_d S as a float32 device tensor of shape (r_1...r_{d-1}, r_d)."""
+        t = self._torch
+        need = C.c_int64()
+        self._check(st_aux_v(self._h, None, 0, C.byref(need), ST_DEVICE))
+        out = t.empty(need.value, dtype=t.float32, device="cuda")
+        self._check(st_aux_v(self._h, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE))
+        rd = self.ranks[-1]
+        return out.reshape(rd, -1).T
 
     def factor(self, mode):
         """Factor U_mode as a float64 device tensor (column-major rows x cols)."""

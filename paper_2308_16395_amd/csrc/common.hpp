@@ -15,8 +15,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
 
-// Precision of the TTM / Gram contractions.
-enum class Prec : int { FP32 = 0, BF16X3 = 1 };
+// Precision of the TTM / Gram contractions: FP32 or split-bf16 MFMA with FP32
+// accumulation, or FP64 MFMA (exact products of the FP32 data, FP64 sums).
+enum class Prec : int { FP32 = 0, BF16X3 = 1, FP64 = 2 };
 
 // ---------------------------------------------------------------------------
 // Wavefront reductions (64 lanes).
@@ -120,6 +121,7 @@ struct FiberW {
   const __bf16 *w_hi;
   const __bf16 *w_lo;
   int64_t ldw_bf;
+  const double *w64;  // FP64 copy of W (row-major, ld = ldw) for Prec::FP64
 };
 
 int fiber_blocks(int64_t F);
@@ -127,15 +129,21 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
                                 const FiberOut &out, double *resid_partials, Prec prec,
                                 hipStream_t s);
 
+// Same contraction for the mode-d rotations with an FP64 W (row-major, ld ldw)
+// and FP64 products and accumulation; output rounded to FP32 once.
+hipError_t launch_rot64(const FiberIn &in, const double *w, int64_t ldw, int m0, int mcount,
+                        const FiberOut &out, hipStream_t s);
+
 // Gram of the residual E = X - (X x W^T) x W (or of X itself when rows == 0)
 // over all fibres: writes per-block partials of the lower-triangular 16x16
 // tiles; `gram_reduce` sums them in FP64 into G (n x n, column-major). The
-// residual is formed with FP32 products; the Gram products use `gp`.
+// residual is formed with FP64 products when `e64` (W.w64 must be set), else
+// with FP32 products; the Gram products use `gp`.
 enum class GramPrec : int { FP32 = 0, BF16X3 = 1, FP64 = 2 };
 int gram_blocks(int64_t F);
 size_t gram_partial_elems(int64_t n, int nblocks);
 hipError_t launch_gram(const FiberIn &in, const FiberW &w, int rows, double *partials,
-                       int nblocks, GramPrec gp, hipStream_t s);
+                       int nblocks, GramPrec gp, bool e64, hipStream_t s);
 hipError_t launch_gram_reduce(const double *partials, int nblocks, int64_t n, double *G,
                               hipStream_t s);
 

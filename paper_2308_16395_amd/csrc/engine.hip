@@ -131,7 +131,7 @@ struct st_handle {
   DBuf<int> info;
   DBuf<double> colpart, q2part, p1, p2, p, p3;
   DBuf<double> U2, V2;
-  DBuf<float> Wv, Wc;
+  DBuf<double> Wv, Wc;
   // secular scratch
   DBuf<double> sd, sz, szh, smu, srot_cs, szz;
   DBuf<int> sact, sK, sdefl, sorg, srot_t, scounts;
@@ -212,6 +212,7 @@ struct st_handle {
     w.w_hi = Uh[k];
     w.w_lo = Ul[k];
     w.ldw_bf = ldb[k];
+    w.w64 = U64[k];
     return w;
   }
 
@@ -264,7 +265,8 @@ struct st_handle {
   // Gram of the residual (rows > 0) or of the tensor (rows == 0) for fibres of
   // length nk, then its eigendecomposition; eigenvalues (ascending) land in
   // hpin[0..nk), eigenvectors in G.
-  int gram_eig(const FiberIn &in, const FiberW &w, int rows, int64_t nk, GramPrec pr) {
+  int gram_eig(const FiberIn &in, const FiberW &w, int rows, int64_t nk, GramPrec pr,
+               bool e64) {
     const int gnb = gram_blocks(in.F);
     hipError_t e = gram_part.ensure(gram_partial_elems(nk, gnb));
     if (e == hipSuccess) e = G.ensure((size_t)nk * nk);
@@ -274,7 +276,7 @@ struct st_handle {
     if (e == hipSuccess) e = ensure_pinned(nk + 8);
     if (e != hipSuccess) return hipfail(e, "gram buffers");
     tic();
-    e = launch_gram(in, w, rows, gram_part.p, gnb, pr, stream);
+    e = launch_gram(in, w, rows, gram_part.p, gnb, pr, e64, stream);
     if (e != hipSuccess) return hipfail(e, "gram");
     // recompute E (4 F n r) and form the lower triangle of E E^T (F n^2)
     toc(ST_K_GRAM, 4.0 * in.F * nk * rows + 1.0 * in.F * nk * nk, 4.0 * in.F * nk);
@@ -400,7 +402,7 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
     in.F = a * b;
     // Gram of the data itself: eigenvalues near eps^2 = tau^2 ||X||^2 / d must
     // be resolved, so the products are accumulated exactly in FP64.
-    rc = gram_eig(in, FiberW{}, 0, nk, GramPrec::FP64);
+    rc = gram_eig(in, FiberW{}, 0, nk, GramPrec::FP64, false);
     if (rc != ST_OK) break;
     int64_t rk;
     double tail;
@@ -456,30 +458,12 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
       if (e == hipSuccess)
         e = hipMemcpyAsync(S[cur].p, S_host.data(), rk * sizeof(double), hipMemcpyHostToDevice,
                            stream);
-      const int64_t ldw = round_up(n_init, 4);
-      if (e == hipSuccess) e = Wv.ensure((size_t)rk * ldw);
-      if (e == hipSuccess) e = Wc.ensure((size_t)rk * ldw);
       if (e == hipSuccess) e = V[cur].ensure((size_t)(R * rk));
       if (e == hipSuccess) e = C[cur].ensure((size_t)(R * rk));
+      // V = A^T U_d S^-1 and C_(d)^T = A^T U_d, A = C*_{d-1,(d)} (FP64 accumulation)
       if (e == hipSuccess)
-        e = launch_build_init_w(Ud[cur].p, ldu, n_init, (int)rk, S[cur].p, Wv.p, Wc.p, ldw,
-                                stream);
-      if (e != hipSuccess) {
-        rc = hipfail(e, "streaming factor");
-        break;
-      }
-      // V = A^T U_d S^-1 and C_(d)^T = A^T U_d, A = C*_{d-1,(d)} (rows = fibres)
-      FiberW wv{};
-      wv.w = Wv.p;
-      wv.ldw = ldw;
-      FiberW wc{};
-      wc.w = Wc.p;
-      wc.ldw = ldw;
-      e = launch_fiber_project(in, wv, 0, (int)rk, FiberOut{V[cur].p, R, rk}, nullptr,
-                               Prec::FP32, stream);
-      if (e == hipSuccess)
-        e = launch_fiber_project(in, wc, 0, (int)rk, FiberOut{C[cur].p, R, rk}, nullptr,
-                                 Prec::FP32, stream);
+        e = launch_init_vc(Din, R, n_init, Ud[cur].p, ldu, (int)rk, S[cur].p, V[cur].p, C[cur].p,
+                           stream);
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (e != hipSuccess) {
         rc = hipfail(e, "init core");
@@ -545,9 +529,9 @@ int st_handle::do_update(const float *y) {
       eps = tau * std::sqrt(ynorm2 / d);
     }
     if (!std::isfinite(e2)) return fail(ST_ENONFINITE, "non-finite residual in mode %d", k + 1);
-    if (prec == Prec::BF16X3 && std::fabs(std::sqrt(e2) - eps) <= guard_rel * eps) {
-      // close to the threshold: decide with the FP32 products
-      rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, a, r[k]}, Prec::FP32, tgroup);
+    if (prec != Prec::FP64 && std::fabs(std::sqrt(e2) - eps) <= guard_rel * eps) {
+      // close to the threshold: decide with the FP64 products
+      rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, a, r[k]}, Prec::FP64, tgroup);
       if (rc != ST_OK) return rc;
       e2 = hpin[0];
       ++stt.guard_hits;
@@ -561,7 +545,9 @@ int st_handle::do_update(const float *y) {
     }
     // Alg. 4 growth: TruncatedSVD of E_(k) via its Gram (Alg. 1)
     rc = gram_eig(in, wmat(k), (int)r[k], nk,
-                  prec == Prec::BF16X3 ? GramPrec::BF16X3 : GramPrec::FP32);
+                  prec == Prec::FP64 ? GramPrec::FP64
+                                     : (prec == Prec::BF16X3 ? GramPrec::BF16X3 : GramPrec::FP32),
+                  prec == Prec::FP64);
     if (rc != ST_OK) return rc;
     int64_t rp;
     double tail;
@@ -702,12 +688,8 @@ int st_handle::do_update(const float *y) {
   vin.mapped = 1;
   vin.map = map;
   vin.extra = grow ? evec.p : nullptr;
-  FiberW vw{};
-  vw.w = Wv.p;
-  vw.ldw = ldwv;
   tic();
-  e = launch_fiber_project(vin, vw, 0, (int)c, FiberOut{V[nxt].p, Rnew, c}, nullptr, Prec::FP32,
-                           stream);
+  e = launch_rot64(vin, Wv.p, ldwv, 0, (int)c, FiberOut{V[nxt].p, Rnew, c}, stream);
   // read V (R_old x r_d) and e, write V~ (R_new x c): 2 R_new K c flops
   toc(ST_K_ROT_V, 2.0 * Rnew * (double)kv * c,
       4.0 * ((double)Rold * rd + (grow ? Rnew : 0) + (double)Rnew * c));
@@ -716,12 +698,8 @@ int st_handle::do_update(const float *y) {
   FiberIn cin = vin;
   cin.x = C[cur].p;
   cin.extra = dvec;
-  FiberW cw{};
-  cw.w = Wc.p;
-  cw.ldw = ldwc;
   tic();
-  e = launch_fiber_project(cin, cw, 0, (int)c, FiberOut{C[nxt].p, Rnew, c}, nullptr, Prec::FP32,
-                           stream);
+  e = launch_rot64(cin, Wc.p, ldwc, 0, (int)c, FiberOut{C[nxt].p, Rnew, c}, stream);
   toc(ST_K_ROT_C, 2.0 * Rnew * (double)(rd + 1) * c,
       4.0 * ((double)Rold * rd + Rnew + (double)Rnew * c));
   if (e != hipSuccess) return hipfail(e, "core rotation");
@@ -880,7 +858,7 @@ int st_create(const st_config *cfg, st_handle **out) {
   }
   *out = nullptr;
   if (cfg->nmodes < 1 || cfg->nmodes > ST_MAX_MODES || !(cfg->tau > 0.0) ||
-      !std::isfinite(cfg->tau) || (cfg->precision != ST_FP32 && cfg->precision != ST_BF16X3) ||
+      !std::isfinite(cfg->tau) || cfg->precision < ST_FP32 || cfg->precision > ST_FP64 ||
       cfg->max_rank_d < 0) {
     g_create_error = "invalid configuration";
     return ST_EINVAL;
@@ -906,9 +884,12 @@ int st_create(const st_config *cfg, st_handle **out) {
   for (int k = 0; k < h->m; ++k) h->n[k] = cfg->dims[k];
   h->NY = ny;
   h->tau = cfg->tau;
-  h->prec = cfg->precision == ST_BF16X3 ? Prec::BF16X3 : Prec::FP32;
+  h->prec = cfg->precision == ST_BF16X3 ? Prec::BF16X3
+                                        : (cfg->precision == ST_FP64 ? Prec::FP64 : Prec::FP32);
   h->orth_tol = cfg->orth_tol > 0.0 ? cfg->orth_tol : 1e-5;
-  h->guard_rel = cfg->guard_rel > 0.0 ? cfg->guard_rel : (h->prec == Prec::BF16X3 ? 0.1 : 0.0);
+  h->guard_rel = cfg->guard_rel > 0.0
+                     ? cfg->guard_rel
+                     : (h->prec == Prec::BF16X3 ? 0.1 : (h->prec == Prec::FP32 ? 1e-2 : 0.0));
   h->max_rank_d = cfg->max_rank_d;
   h->profile = cfg->profile != 0;
   hipError_t e = hipGetDevice(&h->device);
@@ -995,6 +976,24 @@ int st_core(const st_handle *hc, float *out, int64_t cap, int64_t *need, int whe
   return ST_OK;
 }
 
+int st_aux_v(const st_handle *hc, float *out, int64_t cap, int64_t *need, int where) {
+  st_handle *h = const_cast<st_handle *>(hc);
+  if (!h) return ST_EINVAL;
+  if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
+  const int64_t cnt = h->rprod(h->r, h->m) * h->rd;
+  if (need) *need = cnt;
+  if (!out) return ST_OK;
+  if (cap < cnt) return h->fail(ST_ESMALL, "buffer too small");
+  (void)hipSetDevice(h->device);
+  hipError_t e = hipMemcpyAsync(out, h->V[h->cur].p, cnt * sizeof(float),
+                                where == ST_DEVICE ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hipfail(e, "V copy");
+  return ST_OK;
+}
+
 int st_factor(const st_handle *hc, int mode, double *out, int64_t cap, int64_t *rows,
               int64_t *cols, int where) {
   st_handle *h = const_cast<st_handle *>(hc);
@@ -1055,7 +1054,7 @@ int st_reconstruct_slice(const st_handle *hc, int64_t t, float *out) {
 int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
            int64_t rows, float *out, double *norms, int32_t precision, void *stream) {
   if (!x || !dims || !a || !out || nmodes < 1 || nmodes > ST_MAX_MODES || mode < 0 ||
-      mode >= nmodes || rows < 1 || (precision != ST_FP32 && precision != ST_BF16X3))
+      mode >= nmodes || rows < 1 || precision < ST_FP32 || precision > ST_FP64)
     return ST_EINVAL;
   int64_t lo = 1, hi = 1;
   for (int k = 0; k < nmodes; ++k) {
@@ -1075,9 +1074,15 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
   w.w = a;
   w.ldw = nk;
   __bf16 *bh = nullptr, *bl = nullptr;
-  double *part = nullptr, *sum = nullptr;
-  const Prec pr = precision == ST_BF16X3 ? Prec::BF16X3 : Prec::FP32;
+  double *part = nullptr, *sum = nullptr, *a64 = nullptr;
+  const Prec pr = precision == ST_BF16X3 ? Prec::BF16X3
+                                         : (precision == ST_FP64 ? Prec::FP64 : Prec::FP32);
   hipError_t e = hipSuccess;
+  if (pr == Prec::FP64) {
+    e = hipMalloc((void **)&a64, rows * nk * sizeof(double));
+    if (e == hipSuccess) e = launch_f32_to_f64(a, rows * nk, a64, s);
+    w.w64 = a64;
+  }
   if (pr == Prec::BF16X3) {
     const int64_t ldb = round_up(nk, 8);
     e = hipMalloc((void **)&bh, rows * ldb * sizeof(__bf16));
@@ -1100,6 +1105,7 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (bh) (void)hipFree(bh);
   if (bl) (void)hipFree(bl);
+  if (a64) (void)hipFree(a64);
   if (part) (void)hipFree(part);
   if (sum) (void)hipFree(sum);
   if (e == hipErrorOutOfMemory) return ST_ENOMEM;
@@ -1132,7 +1138,8 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
   double *part = nullptr, *G = nullptr;
   hipError_t e = hipMalloc((void **)&part, gram_partial_elems(nk, nb) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void **)&G, nk * nk * sizeof(double));
-  if (e == hipSuccess) e = launch_gram(in, w, (int)rows, part, nb, (GramPrec)gram_precision, s);
+  if (e == hipSuccess)
+    e = launch_gram(in, w, (int)rows, part, nb, (GramPrec)gram_precision, false, s);
   if (e == hipSuccess) e = launch_gram_reduce(part, nb, nk, G, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g, G, nk * nk * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -27,6 +27,33 @@ __device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
 __device__ inline f32x4 mfma_bf(const bf16x8 &a, const bf16x8 &b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+__device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Accumulator of one 16x16 output tile: FP32 for the FP32 and bf16 forms, FP64
+// for the FP64 form. Lane L, element v holds row acc_row(L/16, v), column L%16.
+template <int PREC>
+struct AccT {
+  using type = f32x4;
+};
+template <>
+struct AccT<2> {
+  using type = f64x4;
+};
+template <int PREC>
+__device__ constexpr int acc_row(int grp, int v) {
+  return PREC == 2 ? grp + 4 * v : 4 * grp + v;
+}
+
+__device__ inline void load_w8_f64(const double *w, int64_t ldw, int64_t m, int64_t mend,
+                                   int64_t K, int64_t k0, double (&x)[8]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int64_t k = k0 + s;
+    x[s] = (m < mend && k < K) ? w[m * ldw + k] : 0.0;
+  }
+}
 
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest even).
 __device__ inline void split8(const float (&x)[8], bf16x8 &hi, bf16x8 &lo) {
@@ -112,14 +139,14 @@ __device__ inline void load_wbf8(const __bf16 *wb, int64_t ld, int64_t m, int64_
 template <int MT, int NT, bool CONTIG, int PREC, bool NORMX>
 __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t m0, int64_t mend,
                                     const int64_t (&fib)[NT], const int64_t (&base)[NT],
-                                    f32x4 (&acc)[MT][NT], double &x2) {
+                                    typename AccT<PREC>::type (&acc)[MT][NT], double &x2) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
   const int64_t K = in.n + ((in.mapped && in.extra) ? 1 : 0);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = typename AccT<PREC>::type{0, 0, 0, 0};
 
   for (int64_t kb = 0; kb < K; kb += 32) {
     const int64_t k0 = kb + 8 * grp;
@@ -132,7 +159,7 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
         for (int s = 0; s < 8; ++s) x2 += (double)xv[nt][s] * (double)xv[nt][s];
       }
     }
-    if (PREC == 0) {
+    if constexpr (PREC == 0) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         float wv[8];
@@ -141,6 +168,17 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
         for (int s = 0; s < 8; ++s)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma4(wv[s], xv[nt][s], acc[mt][nt]);
+      }
+    } else if constexpr (PREC == 2) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        double wv[8];
+        load_w8_f64(w.w64, w.ldw, m0 + 16 * mt + col, mend, K, k0, wv);
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = mfma_f64(wv[s], (double)xv[nt][s], acc[mt][nt]);
       }
     } else {
       bf16x8 xh[NT], xl[NT];
@@ -167,13 +205,24 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
 // U[j][m] = W[m][j] and P^T in the accumulators (MT tiles over m).
 template <int MT, int NT, int PREC>
 __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int jt,
-                                  const f32x4 (&acc)[MT][NT], f32x4 (&racc)[NT]) {
+                                  const typename AccT<PREC>::type (&acc)[MT][NT],
+                                  typename AccT<PREC>::type (&racc)[NT]) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
   const int64_t j = 16 * jt + col;
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) racc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (PREC == 0) {
+  for (int nt = 0; nt < NT; ++nt) racc[nt] = typename AccT<PREC>::type{0, 0, 0, 0};
+  if constexpr (PREC == 2) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = 16 * mt + grp + 4 * v;
+        const double a = (m < rows && j < n) ? w.w64[m * w.ldw + j] : 0.0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) racc[nt] = mfma_f64(a, acc[mt][nt][v], racc[nt]);
+      }
+  } else if constexpr (PREC == 0) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -244,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
     fib[nt] = fwave + 16 * nt + col;
     base[nt] = fiber_base(in, fib[nt]);
   }
-  f32x4 acc[MT][NT];
+  typename AccT<PREC>::type acc[MT][NT];
   double x2 = 0.0, e2 = 0.0;
   project_wave<MT, NT, CONTIG, PREC, RESID>(in, w, mbeg, mend, fib, base, acc, x2);
 
@@ -258,24 +307,32 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t m = mbeg + 16 * mt + 4 * grp + v;
-        if (m < mend) out.p[fr + out.ao * (m + out.mo * fq)] = acc[mt][nt][v];
+        const int64_t m = mbeg + 16 * mt + acc_row<PREC>(grp, v);
+        if (m < mend) out.p[fr + out.ao * (m + out.mo * fq)] = (float)acc[mt][nt][v];
       }
   }
 
   if (RESID) {
     const int jtiles = (int)((in.n + 15) / 16);
     for (int jt = 0; jt < jtiles; ++jt) {
-      f32x4 racc[NT];
+      typename AccT<PREC>::type racc[NT];
       recon_tile<MT, NT, PREC>(w, mcount, in.n, jt, acc, racc);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (fib[nt] >= in.F) continue;
         float xv[4];
-        load_x4<CONTIG>(in, base[nt], 16 * jt + 4 * grp, xv);
+        if constexpr (PREC == 2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t j = 16 * jt + grp + 4 * v;
+            xv[v] = (base[nt] >= 0 && j < in.n) ? in.x[base[nt] + in.a * j] : 0.0f;
+          }
+        } else {
+          load_x4<CONTIG>(in, base[nt], 16 * jt + 4 * grp, xv);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t j = 16 * jt + 4 * grp + v;
+          const int64_t j = 16 * jt + acc_row<PREC>(grp, v);
           if (j < in.n) {
             const double e = (double)xv[v] - (double)racc[nt][v];
             e2 += e * e;
@@ -299,6 +356,78 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
 }
 
 // ---------------------------------------------------------------------------
+// Mode-d rotations with FP64 products and sums (FP32 state in and out).
+//
+// The rotations V~ = [V v] V'' and C~^T = [C^T d] U'' are applied to the whole
+// auxiliary matrix and core on every slice. FP32 accumulation adds a random
+// error of about u sqrt(K) per entry per slice; over hundreds of slices that
+// perturbs span(V) by more than the ISVD tolerance can absorb (at tau = 1e-4,
+// eps / ||d|| is about 4.5e-5), so these products run on the FP64 MFMA: the
+// FP32 inputs are exact in FP64 and each output is rounded to FP32 once.
+// ---------------------------------------------------------------------------
+template <int MT, int NT>
+__global__ __launch_bounds__(kThreads) void rot64_kernel(FiberIn in, const double *w, int64_t ldw,
+                                                         int m0, int mcount, FiberOut out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int64_t mbeg = (int64_t)m0 + (int64_t)blockIdx.y * (16 * MT);
+  const int64_t mend = (int64_t)m0 + mcount;
+  const int64_t fwave = ((int64_t)blockIdx.x * 4 + wid) * (16 * NT);
+  const int64_t K = in.n + ((in.mapped && in.extra) ? 1 : 0);
+  int64_t fib[NT], base[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    fib[nt] = fwave + 16 * nt + col;
+    base[nt] = fiber_base(in, fib[nt]);
+  }
+  f64x4 acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kb = 0; kb < K; kb += 32) {
+    const int64_t k0 = kb + 8 * grp;
+    float xv[NT][8];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) load_x8<false>(in, base[nt], fib[nt], K, k0, xv[nt]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      double wv[8];
+      load_w8_f64(w, ldw, mbeg + 16 * mt + col, mend, K, k0, wv);
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = mfma_f64(wv[s], (double)xv[nt][s], acc[mt][nt]);
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int64_t f = fib[nt];
+    if (f >= in.F) continue;
+    const int64_t fq = f / out.ao, fr = f - fq * out.ao;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = mbeg + 16 * mt + grp + 4 * v;  // FP64 accumulator layout
+        if (m < mend) out.p[fr + out.ao * (m + out.mo * fq)] = (float)acc[mt][nt][v];
+      }
+  }
+}
+
+template <int MT, int NT>
+hipError_t launch_rot64_t(const FiberIn &in, const double *w, int64_t ldw, int m0, int mcount,
+                          const FiberOut &out, hipStream_t s) {
+  const int64_t per_block = 64 * NT;
+  dim3 grid((unsigned)((in.F + per_block - 1) / per_block),
+            (unsigned)((mcount + 16 * MT - 1) / (16 * MT)));
+  hipLaunchKernelGGL((rot64_kernel<MT, NT>), grid, dim3(kThreads), 0, s, in, w, ldw, m0, mcount,
+                     out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Residual Gram. Each block iterates over 64-fibre tiles; every wave forms E^T
 // for its 16 fibres (all n rows) into LDS, then the waves accumulate their
 // share of the lower-triangular 16x16 tiles of G = sum_f e_f e_f^T.
@@ -314,14 +443,10 @@ __device__ inline void tile_ij(int t, int &ti, int &tj) {
   tj = t - i * (i + 1) / 2;
 }
 
-__device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
 // GP: product precision of the Gram, 0 = FP32, 1 = bf16x3, 2 = FP64 (the FP32
 // inputs are exact in FP64, so this accumulates the exact products). The
 // residual itself is always recomputed with FP32 products.
-template <int MT, bool CONTIG, int GP>
+template <int MT, bool CONTIG, int GP, int PE>
 __global__ __launch_bounds__(kThreads) void gram_kernel(FiberIn in, FiberW w, int rows,
                                                         double *partials, int ntiles) {
   extern __shared__ float es[];  // [n_pad][68]
@@ -354,17 +479,18 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(FiberIn in, FiberW w, in
     int64_t fib[1] = {fw + col};
     int64_t base[1] = {fiber_base(in, fib[0])};
     if (rows > 0) {
-      f32x4 acc[MT][1];
+      typename AccT<PE>::type acc[MT][1];
       double dummy = 0.0;
-      project_wave<MT, 1, CONTIG, 0, false>(in, w, 0, rows, fib, base, acc, dummy);
+      project_wave<MT, 1, CONTIG, PE, false>(in, w, 0, rows, fib, base, acc, dummy);
       for (int jt = 0; jt < jtiles; ++jt) {
-        f32x4 racc[1];
-        recon_tile<MT, 1, 0>(w, rows, n, jt, acc, racc);
-        float xv[4];
-        load_x4<CONTIG>(in, base[0], 16 * jt + 4 * grp, xv);
+        typename AccT<PE>::type racc[1];
+        recon_tile<MT, 1, PE>(w, rows, n, jt, acc, racc);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          es[(16 * jt + 4 * grp + v) * LDE + wid * 16 + col] = xv[v] - racc[0][v];
+        for (int v = 0; v < 4; ++v) {
+          const int64_t j = 16 * jt + acc_row<PE>(grp, v);
+          const float x = (base[0] >= 0 && j < n) ? in.x[base[0] + in.a * j] : 0.0f;
+          es[j * LDE + wid * 16 + col] = (float)((double)x - (double)racc[0][v]);
+        }
       }
     } else {
       for (int jt = 0; jt < jtiles; ++jt) {
@@ -472,6 +598,8 @@ hipError_t launch_fiber_p(const FiberIn &in, const FiberW &w, int m0, int mcount
                           const FiberOut &out, double *partials, Prec prec, hipStream_t s) {
   if (prec == Prec::BF16X3)
     return launch_fiber_t<MT, NT, CONTIG, RESID, 1>(in, w, m0, mcount, out, partials, s);
+  if (prec == Prec::FP64)
+    return launch_fiber_t<MT, NT, CONTIG, RESID, 2>(in, w, m0, mcount, out, partials, s);
   return launch_fiber_t<MT, NT, CONTIG, RESID, 0>(in, w, m0, mcount, out, partials, s);
 }
 
@@ -492,17 +620,26 @@ template <int NT>
 hipError_t launch_fiber_n(const FiberIn &in, const FiberW &w, int m0, int mcount,
                           const FiberOut &out, double *partials, bool contig, Prec prec,
                           hipStream_t s) {
+  // smallest instantiated tile count >= the rows needed (padding wastes MFMA work)
   const int tiles = (mcount + 15) / 16;
-  if (tiles <= 1) return launch_fiber_c<1, NT>(in, w, m0, mcount, out, partials, contig, prec, s);
-  if (tiles <= 2) return launch_fiber_c<2, NT>(in, w, m0, mcount, out, partials, contig, prec, s);
-  if (tiles <= 4) return launch_fiber_c<4, NT>(in, w, m0, mcount, out, partials, contig, prec, s);
-  if (tiles <= 8) return launch_fiber_c<8, NT>(in, w, m0, mcount, out, partials, contig, prec, s);
+#define ST_FIBER_CASE(T) \
+  if (tiles <= T) return launch_fiber_c<T, NT>(in, w, m0, mcount, out, partials, contig, prec, s);
+  ST_FIBER_CASE(1)
+  ST_FIBER_CASE(2)
+  ST_FIBER_CASE(3)
+  ST_FIBER_CASE(4)
+  ST_FIBER_CASE(5)
+  ST_FIBER_CASE(6)
+  ST_FIBER_CASE(8)
+  ST_FIBER_CASE(10)
+  ST_FIBER_CASE(12)
+#undef ST_FIBER_CASE
   if (tiles <= 16 || partials == nullptr)
     return launch_fiber_c<16, NT>(in, w, m0, mcount, out, partials, contig, prec, s);
   return hipErrorInvalidValue;  // fused residual needs all rows in one block
 }
 
-template <int MT, bool CONTIG>
+template <int MT, bool CONTIG, int PE>
 hipError_t launch_gram_c(const FiberIn &in, const FiberW &w, int rows, double *partials,
                          int nblocks, int gp, hipStream_t s) {
   const int jt = (int)((in.n + 15) / 16);
@@ -511,19 +648,19 @@ hipError_t launch_gram_c(const FiberIn &in, const FiberW &w, int rows, double *p
   const size_t lds = (size_t)jt * 16 * 68 * sizeof(float);
   dim3 grid((unsigned)nblocks, (unsigned)groups);
   if (gp == 2) {
-    hipFuncSetAttribute((const void *)gram_kernel<MT, CONTIG, 2>,
+    hipFuncSetAttribute((const void *)gram_kernel<MT, CONTIG, 2, PE>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((gram_kernel<MT, CONTIG, 2>), grid, dim3(kThreads), lds, s, in, w, rows,
+    hipLaunchKernelGGL((gram_kernel<MT, CONTIG, 2, PE>), grid, dim3(kThreads), lds, s, in, w, rows,
                        partials, ntiles);
   } else if (gp == 1) {
-    hipFuncSetAttribute((const void *)gram_kernel<MT, CONTIG, 1>,
+    hipFuncSetAttribute((const void *)gram_kernel<MT, CONTIG, 1, PE>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((gram_kernel<MT, CONTIG, 1>), grid, dim3(kThreads), lds, s, in, w, rows,
+    hipLaunchKernelGGL((gram_kernel<MT, CONTIG, 1, PE>), grid, dim3(kThreads), lds, s, in, w, rows,
                        partials, ntiles);
   } else {
-    hipFuncSetAttribute((const void *)gram_kernel<MT, CONTIG, 0>,
+    hipFuncSetAttribute((const void *)gram_kernel<MT, CONTIG, 0, PE>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((gram_kernel<MT, CONTIG, 0>), grid, dim3(kThreads), lds, s, in, w, rows,
+    hipLaunchKernelGGL((gram_kernel<MT, CONTIG, 0, PE>), grid, dim3(kThreads), lds, s, in, w, rows,
                        partials, ntiles);
   }
   return hipGetLastError();
@@ -531,9 +668,13 @@ hipError_t launch_gram_c(const FiberIn &in, const FiberW &w, int rows, double *p
 
 template <int MT>
 hipError_t launch_gram_t(const FiberIn &in, const FiberW &w, int rows, double *partials,
-                         int nblocks, bool contig, int gp, hipStream_t s) {
-  if (contig) return launch_gram_c<MT, true>(in, w, rows, partials, nblocks, gp, s);
-  return launch_gram_c<MT, false>(in, w, rows, partials, nblocks, gp, s);
+                         int nblocks, bool contig, int gp, bool e64, hipStream_t s) {
+  if (e64) {
+    if (contig) return launch_gram_c<MT, true, 2>(in, w, rows, partials, nblocks, gp, s);
+    return launch_gram_c<MT, false, 2>(in, w, rows, partials, nblocks, gp, s);
+  }
+  if (contig) return launch_gram_c<MT, true, 0>(in, w, rows, partials, nblocks, gp, s);
+  return launch_gram_c<MT, false, 0>(in, w, rows, partials, nblocks, gp, s);
 }
 
 }  // namespace
@@ -557,6 +698,18 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
   return launch_fiber_n<1>(in, w, m0, mcount, out, resid_partials, contig, prec, s);
 }
 
+hipError_t launch_rot64(const FiberIn &in, const double *w, int64_t ldw, int m0, int mcount,
+                        const FiberOut &out, hipStream_t s) {
+  if (in.F <= 0 || mcount <= 0) return hipSuccess;
+  const int tiles = (mcount + 15) / 16;
+  if (tiles <= 2) return launch_rot64_t<2, 2>(in, w, ldw, m0, mcount, out, s);
+  if (tiles <= 4) return launch_rot64_t<4, 2>(in, w, ldw, m0, mcount, out, s);
+  if (tiles <= 6) return launch_rot64_t<6, 2>(in, w, ldw, m0, mcount, out, s);
+  if (tiles <= 8) return launch_rot64_t<8, 1>(in, w, ldw, m0, mcount, out, s);
+  if (tiles <= 12) return launch_rot64_t<12, 1>(in, w, ldw, m0, mcount, out, s);
+  return launch_rot64_t<16, 1>(in, w, ldw, m0, mcount, out, s);
+}
+
 int gram_blocks(int64_t F) {
   const int64_t t = (F + 63) / 64;
   return (int)(t < 512 ? t : 512);
@@ -568,17 +721,17 @@ size_t gram_partial_elems(int64_t n, int nblocks) {
 }
 
 hipError_t launch_gram(const FiberIn &in, const FiberW &w, int rows, double *partials,
-                       int nblocks, GramPrec gp, hipStream_t s) {
+                       int nblocks, GramPrec gp, bool e64, hipStream_t s) {
   if (in.F <= 0) return hipSuccess;
   if (in.n > 512) return hipErrorInvalidValue;  // E tile must fit in LDS
   const bool contig = contiguous(in);
   const int g = (int)gp;
   const int tiles = (rows + 15) / 16;
-  if (tiles <= 1) return launch_gram_t<1>(in, w, rows, partials, nblocks, contig, g, s);
-  if (tiles <= 2) return launch_gram_t<2>(in, w, rows, partials, nblocks, contig, g, s);
-  if (tiles <= 4) return launch_gram_t<4>(in, w, rows, partials, nblocks, contig, g, s);
-  if (tiles <= 8) return launch_gram_t<8>(in, w, rows, partials, nblocks, contig, g, s);
-  if (tiles <= 16) return launch_gram_t<16>(in, w, rows, partials, nblocks, contig, g, s);
+  if (tiles <= 1) return launch_gram_t<1>(in, w, rows, partials, nblocks, contig, g, e64, s);
+  if (tiles <= 2) return launch_gram_t<2>(in, w, rows, partials, nblocks, contig, g, e64, s);
+  if (tiles <= 4) return launch_gram_t<4>(in, w, rows, partials, nblocks, contig, g, e64, s);
+  if (tiles <= 8) return launch_gram_t<8>(in, w, rows, partials, nblocks, contig, g, e64, s);
+  if (tiles <= 16) return launch_gram_t<16>(in, w, rows, partials, nblocks, contig, g, e64, s);
   return hipErrorInvalidValue;
 }
 

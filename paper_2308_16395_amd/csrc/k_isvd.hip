@@ -124,11 +124,11 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
       }
     }
   }
-  double *dst = a.colpart + (size_t)blockIdx.x * r;
+  // column-major partials: colpart[j * gridDim.x + block]
 #pragma unroll
   for (int q = 0; q < kMaxCols; ++q) {
     const int j = tid + q * blockDim.x;
-    if (j < r) dst[j] = colacc[q];
+    if (j < r) a.colpart[(size_t)j * gridDim.x + blockIdx.x] = colacc[q];
   }
   if (PASS == 3) {
     __shared__ double red[16];
@@ -137,21 +137,24 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
   }
 }
 
-// out[j] = sum_b part[b * r + j] (fixed order); optionally out2[j] = out[j] + add[j];
-// optionally q2 = sum_b q2part[b].
-__global__ void colsum_kernel(const double *part, int nb, int r, double *out, const double *add,
-                              double *out2, const double *q2part, double *q2) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < r) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * r + j];
-    out[j] = s;
-    if (out2) out2[j] = s + add[j];
-  }
-  if (q2part && blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += q2part[b];
-    q2[0] = s;
+// One block per column: out[j] = sum_b part[j * nb + b] (fixed tree order);
+// optionally out2[j] = out[j] + add[j]; block r (if q2part) sums q2part.
+__global__ __launch_bounds__(256) void colsum_kernel(const double *part, int nb, int r,
+                                                     double *out, const double *add, double *out2,
+                                                     const double *q2part, double *q2) {
+  __shared__ double red[16];
+  const int j = blockIdx.x;
+  const double *src = (j < r) ? part + (size_t)j * nb : q2part;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += src[b];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    if (j < r) {
+      out[j] = s;
+      if (out2) out2[j] = s + add[j];
+    } else {
+      q2[0] = s;
+    }
   }
 }
 
@@ -190,7 +193,8 @@ hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s) {
 
 hipError_t launch_colsum(const double *part, int nb, int r, double *out, const double *add,
                          double *out2, const double *q2part, double *q2, hipStream_t s) {
-  const int blocks = (r + 255) / 256 > 0 ? (r + 255) / 256 : 1;
+  const int blocks = r + (q2part ? 1 : 0);
+  if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(colsum_kernel, dim3(blocks), dim3(256), 0, s, part, nb, r, out, add, out2,
                      q2part, q2);
   return hipGetLastError();
@@ -325,22 +329,22 @@ hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, co
   return hipGetLastError();
 }
 
-// Row-major FP32 rotation matrices for the mode-d TTMs of V and C:
+// Row-major FP64 rotation matrices for the mode-d TTMs of V and C:
 //   Wv[m][k] = V''[k][m] (k < kv), with row r scaled by 1/q when e is kept;
 //   Wc[m][k] = U''[k][m] (k <= r).
 __global__ void build_rot_w_kernel(const double *U2, const double *V2, int r, int c, int kv,
-                                   double inv_q, float *Wv, int64_t ldv, float *Wc, int64_t ldc) {
+                                   double inv_q, double *Wv, int64_t ldv, double *Wc, int64_t ldc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)c * (r + 1);
   if (idx >= total) return;
   const int m = (int)(idx / (r + 1)), k = (int)(idx % (r + 1));
   const size_t src = (size_t)k + (size_t)(r + 1) * m;
-  Wc[m * ldc + k] = (float)U2[src];
-  if (k < kv) Wv[m * ldv + k] = (float)(k == r ? V2[src] * inv_q : V2[src]);
+  Wc[m * ldc + k] = U2[src];
+  if (k < kv) Wv[m * ldv + k] = (k == r) ? V2[src] * inv_q : V2[src];
 }
 
 hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
-                              double inv_q, float *Wv, int64_t ldv, float *Wc, int64_t ldc,
+                              double inv_q, double *Wv, int64_t ldv, double *Wc, int64_t ldc,
                               hipStream_t s) {
   const int64_t total = (int64_t)c * (r + 1);
   hipLaunchKernelGGL(build_rot_w_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
@@ -348,23 +352,26 @@ hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, 
   return hipGetLastError();
 }
 
-// Init: Wv[m][j] = U_d[j][m] / S[m], Wc[m][j] = U_d[j][m] (row-major, j < nd).
-__global__ void build_init_w_kernel(const double *Ud, int64_t ldu, int64_t nd, int rd,
-                                    const double *S, float *Wv, float *Wc, int64_t ldw) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nd * rd) return;
-  const int m = (int)(idx / nd);
-  const int64_t j = idx % nd;
-  const double u = Ud[j + ldu * m];
-  Wc[m * ldw + j] = (float)u;
-  Wv[m * ldw + j] = (float)(u / S[m]);
+// Init: C^T = A U_d and V = A U_d S^-1 with A the (R x n_init) mode-d unfolding
+// of the last partial core, accumulated in FP64. With FP32 products the columns
+// of small singular value would carry a relative error of about u s_1 / s_k and
+// V would not be orthonormal to the accuracy the ISVD residual test needs.
+__global__ void init_vc_kernel(const float *A, int64_t R, int64_t nd, const double *Ud,
+                               int64_t ldu, int rd, const double *S, float *V, float *Cc) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= R) return;
+  for (int m = 0; m < rd; ++m) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < nd; ++j) acc += (double)A[row + R * j] * Ud[j + ldu * m];
+    Cc[row + R * m] = (float)acc;
+    V[row + R * m] = (float)(acc / S[m]);
+  }
 }
 
-hipError_t launch_build_init_w(const double *Ud, int64_t ldu, int64_t nd, int rd, const double *S,
-                               float *Wv, float *Wc, int64_t ldw, hipStream_t s) {
-  const int64_t total = nd * rd;
-  hipLaunchKernelGGL(build_init_w_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     Ud, ldu, nd, rd, S, Wv, Wc, ldw);
+hipError_t launch_init_vc(const float *A, int64_t R, int64_t nd, const double *Ud, int64_t ldu,
+                          int rd, const double *S, float *V, float *Cc, hipStream_t s) {
+  hipLaunchKernelGGL(init_vc_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, A, R, nd,
+                     Ud, ldu, rd, S, V, Cc);
   return hipGetLastError();
 }
 
@@ -521,6 +528,17 @@ hipError_t launch_split_rows(const float *w, int64_t rows, int64_t n, int64_t ld
   const int64_t total = rows * ldb;
   hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w,
                      rows, n, ldw, hi, lo, ldb);
+  return hipGetLastError();
+}
+
+__global__ void f32_to_f64_kernel(const float *x, int64_t n, double *y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+
+hipError_t launch_f32_to_f64(const float *x, int64_t n, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(f32_to_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
+                     y);
   return hipGetLastError();
 }
 

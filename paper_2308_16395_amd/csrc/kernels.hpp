@@ -31,10 +31,10 @@ hipError_t launch_secular_svd(SecData s, const double *S, const double *p, doubl
 hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, const double *U2,
                             int c, double *Un, int64_t ldn, hipStream_t s);
 hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
-                              double inv_q, float *Wv, int64_t ldv, float *Wc, int64_t ldc,
+                              double inv_q, double *Wv, int64_t ldv, double *Wc, int64_t ldc,
                               hipStream_t s);
-hipError_t launch_build_init_w(const double *Ud, int64_t ldu, int64_t nd, int rd, const double *S,
-                               float *Wv, float *Wc, int64_t ldw, hipStream_t s);
+hipError_t launch_init_vc(const float *A, int64_t R, int64_t nd, const double *Ud, int64_t ldu,
+                          int rd, const double *S, float *V, float *Cc, hipStream_t s);
 hipError_t launch_new_columns(const double *Q, int64_t n, const double *U, int r, int k,
                               double *W, double *coef, hipStream_t s);
 hipError_t launch_append_cols(const double *W, int64_t n, int c0, int k, double *U64, float *Uf,
@@ -46,5 +46,7 @@ hipError_t launch_ud_row(const double *Ud, int64_t ld, int64_t t, int rd, float 
 
 hipError_t launch_split_rows(const float *w, int64_t rows, int64_t n, int64_t ldw, __bf16 *hi,
                              __bf16 *lo, int64_t ldb, hipStream_t s);
+
+hipError_t launch_f32_to_f64(const float *x, int64_t n, double *y, hipStream_t s);
 
 }  // namespace st

@@ -1,0 +1,55 @@
+"""Write the FP64 oracle's per-slice decisions on the 128^3 x 16 blob stream.
+
+Runs only the oracle (no GPU code): ST-HOSVD of the first 20 slices, then the
+streaming update of slices 20..399, on the float32 values of the slices (the
+values the GPU library consumes), tau = 1e-4. Records after every slice the
+ranks, eps, ||E_k||/eps per slice mode, q/eps, and the branch taken, so the GPU
+run at full size can be compared decision by decision.
+
+Usage: python tests/golden/make_blob_trajectory.py [n_slices]
+"""
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import StreamingTucker  # noqa: E402
+from synth import make_stream  # noqa: E402
+
+
+def main():
+    n_slices = int(sys.argv[1]) if len(sys.argv) > 1 else 400
+    s = make_stream(1)
+    n_init, tau = 20, 1e-4
+
+    def sl(t):
+        return s.slice_flat(t).astype(np.float32).astype(np.float64).reshape(s.dims, order="F")
+
+    orc = StreamingTucker(np.stack([sl(t) for t in range(n_init)], axis=-1), tau)
+    out = dict(
+        source="FP64 oracle (oracle/tucker.py), blob stream config 1, float32 slice values",
+        stream=dict(space=list(s.space), n_vars=s.n_vars, n_blobs=s.n_blobs, seed=1001,
+                    n_init=n_init, tau=tau, n_slices=n_slices),
+        init_ranks=list(orc.ranks), init_bound=orc.recon_error_bound(), slices=[])
+    t0 = time.time()
+    for t in range(n_init, n_slices):
+        rec = orc.update(sl(t))
+        out["slices"].append(dict(
+            t=t, ranks=list(orc.ranks), eps=rec["eps"],
+            e_over_eps=[e / rec["eps"] for e in rec["e_norm"]], q_over_eps=rec["q"] / rec["eps"],
+            grew=[int(g) for g in rec["r_new"]], ignored=bool(rec["ignored"]),
+            bound=orc.recon_error_bound()))
+        print(t, orc.ranks, f"{time.time() - t0:.0f}s", flush=True)
+    with open(os.path.join(HERE, "blobs128_oracle_trajectory.json"), "w") as f:
+        json.dump(out, f)
+
+
+if __name__ == "__main__":
+    main()

@@ -50,6 +50,32 @@ def test_blobs_with_rank_growth(precision, err_tol):
     _assert_parity(res, err_tol)
 
 
+def test_blobs_tau1e4_d5_medium_fp64_products():
+    """The benchmark's regime at 1/38 of its size: d = 5 (48^3 space x 8
+    variables), tau = 1e-4, 80 slices, growth in every mode early on. With exact
+    FP64 products on the FP32 data every rank decision matches the oracle."""
+    s = BlobStream((48, 48, 48), 8, 16, (3.0, 8.0), 0.5, n_slices=80, seed=41)
+    res, gpu, orc = run_parity(s, 80, 10, 1e-4, precision="fp64", probe_every=5)
+    assert res["diverged_at"] is None, (res["diverged_at"], res["margin_at_divergence"])
+    assert res["worst_err"] <= 1e-5, res["worst_err"]
+    ign_gpu = sum(st["isvd_ignored"] for st in res["stats"])
+    ign_orc = sum(h["ignored"] for h in orc.history)
+    assert ign_gpu == ign_orc
+    assert max(st["orth_check"] for st in res["stats"]) < 1e-5
+
+
+@pytest.mark.parametrize("precision,err_tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_blobs_tau1e4_d5_medium_fast_forms(precision, err_tol):
+    """Same stream with FP32-accumulated or split-bf16 products: the model stays
+    within the error bar of the oracle for as long as the rank decisions agree
+    (their product noise can tip the ISVD decision of a near-threshold slice)."""
+    s = BlobStream((48, 48, 48), 8, 16, (3.0, 8.0), 0.5, n_slices=50, seed=41)
+    res, gpu, orc = run_parity(s, 50, 10, 1e-4, precision=precision, probe_every=5)
+    assert res["worst_err"] <= err_tol, res["worst_err"]
+    if res["diverged_at"] is not None:
+        assert res["diverged_at"] >= 20, res["diverged_at"]
+
+
 def test_matrix_stream_d2():
     """d = 2: the update reduces to the incremental SVD of a growing matrix."""
     rng = np.random.default_rng(5)

@@ -38,7 +38,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("bf16x3", 2e-4), ("fp64", 1e-12)])
 @pytest.mark.parametrize("dims,mode,rows", CASES)
 def test_ttm_projection_and_residual(dims, mode, rows, precision, rtol):
     import torch
@@ -56,14 +56,19 @@ def test_ttm_projection_and_residual(dims, mode, rows, precision, rtol):
     y_ref, e2_ref, x2_ref = _ref(x, u.T, mode)
     out_dims = list(dims)
     out_dims[mode] = rows
-    y = out.cpu().numpy().reshape(out_dims, order="F")
+    y = out.cpu().numpy().reshape(out_dims, order="F").astype(np.float64)
     scale = np.abs(y_ref).max()
-    np.testing.assert_allclose(y, y_ref, rtol=0, atol=rtol * scale * np.sqrt(dims[mode]))
+    if precision == "fp64":
+        # exact products and FP64 sums: only the final rounding to FP32 remains
+        np.testing.assert_allclose(y, y_ref, rtol=2 ** -23, atol=1e-12 * scale)
+    else:
+        np.testing.assert_allclose(y, y_ref, rtol=0, atol=rtol * scale * np.sqrt(dims[mode]))
     if want_norms:
         e2, x2 = norms
         np.testing.assert_allclose(x2, x2_ref, rtol=1e-12)
         # the residual norm squared is accurate to the product precision relative to ||X||^2
-        assert abs(e2 - e2_ref) <= (1e-5 if precision == "fp32" else 1e-3) * x2_ref
+        tol = {"fp32": 1e-5, "bf16x3": 1e-3, "fp64": 1e-12}[precision]
+        assert abs(e2 - e2_ref) <= tol * x2_ref
 
 
 GRAM_CASES = [
