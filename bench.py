@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 METRIC = "slices/s at eps-bounded error: bf16x3 MFMA vs FP32 path; TTM/Gram % roofline"
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0 / 3.0, "fp64": 78.6}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "blobs128_oracle_trajectory.json")
 
 WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_init=20,
                 tau=1e-4, seed=1001)
@@ -45,8 +46,7 @@ def roofline(prof, precision):
         return group, None
     sec = p["ms"] / 1e3
     ai = p["flops"] / p["bytes"] if p["bytes"] else float("inf")
-    prec_key = "fp64" if group in ("eig", "svd", "ud") else (
-        precision if group in ("ttm1", "ttm", "ttm_ext", "gram") else "fp32")
+    prec_key = "fp64" if group in ("eig", "svd", "ud", "rot_v", "rot_c", "isvd") else precision
     peak_f = PEAK_TFLOPS[prec_key]
     ridge = peak_f * 1e12 / (PEAK_HBM_GBS * 1e9)
     if ai >= ridge:
@@ -94,10 +94,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=375)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32")
     ap.add_argument("--cpu-updates", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the streaming update is sequential along the "
@@ -127,38 +128,65 @@ def main():
         data[t] = stream.slice_torch(t, dev, torch.float32)
     torch.cuda.synchronize()
 
-    st = pkg.StreamingTucker(stream.dims, w["tau"], precision=args.precision, profile=True)
-    t0 = time.perf_counter()
-    st.init(data[:n_init].reshape(-1), n_init)
-    init_s = time.perf_counter() - t0
-    log(f"init {init_s:.2f} s, ranks {st.ranks}")
-    for t in range(n_init, n_init + args.warmup):
-        st.update(data[t])
-    st.profile(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(n_init + args.warmup, total):
-        st.update(data[t])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = st.profile()
-    log(f"timed {args.steps} updates in {dt:.3f} s, ranks {st.ranks}")
+    golden = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            golden = json.load(f)
 
-    value = args.steps / dt
+    def run(precision, want_profile):
+        st = pkg.StreamingTucker(stream.dims, w["tau"], precision=precision, profile=True)
+        t0 = time.perf_counter()
+        st.init(data[:n_init].reshape(-1), n_init)
+        init_s = time.perf_counter() - t0
+        traj = []
+        for t in range(n_init, n_init + args.warmup):
+            st.update(data[t])
+            traj.append(st.ranks)
+        st.profile(reset=True)
+        ranks = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(n_init + args.warmup, total):
+            st.update(data[t])
+            ranks.append(st.ranks)  # host-side counters only, no device sync
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        traj += ranks
+        prof = st.profile()
+        info = dict(value=round(args.steps / dt, 3), ms_per_step=round(1e3 * dt / args.steps, 4),
+                    init_s=round(init_s, 3), ranks_final=list(st.ranks),
+                    recon_error_bound=st.recon_error()[0])
+        if golden is not None:
+            ref = [tuple(x["ranks"]) for x in golden["slices"]][:len(traj)]
+            first = next((i for i, (a, b) in enumerate(zip(traj, ref)) if tuple(a) != b), None)
+            info["ranks_match_oracle"] = first is None
+            info["first_rank_divergence_slice"] = None if first is None else n_init + first
+        if not args.no_accuracy:
+            err2 = nrm2 = 0.0
+            for t in range(total):
+                rec = st.reconstruct_slice(t)
+                err2 += torch.sum((rec.double() - data[t].double()) ** 2).item()
+                nrm2 += torch.sum(data[t].double() ** 2).item()
+            info["true_rel_error"] = math.sqrt(err2 / nrm2)
+            info["eps_met"] = info["true_rel_error"] <= w["tau"]
+        st.close()
+        log(f"{precision}: {info}")
+        return info, prof
+
+    head, prof = run(args.precision, True)
     group, roof = roofline(prof, args.precision)
-    bound, _ = st.recon_error()
     result = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "slices/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": "advecting-blobs 128x128x128 x 16 variables, 400 slices, tau 1e-4, "
@@ -167,30 +195,28 @@ def main():
             "eps": w["tau"], "precision": args.precision, "seed": w["seed"],
         },
         "roofline": roof,
-        "ranks_final": list(st.ranks),
-        "recon_error_bound": bound,
-        "init_s": round(init_s, 3),
         "kernels": {g: dict(launches=p["launches"], ms=round(p["ms"], 3),
                             tflops=round(p["flops"] / p["ms"] / 1e9, 3) if p["ms"] else None,
                             gbs=round(p["bytes"] / p["ms"] / 1e6, 1) if p["ms"] else None)
                     for g, p in prof.items() if p["launches"]},
     }
-    if not args.no_accuracy:
-        # true relative error of the model over every slice seen (outside the timed region)
-        err2 = nrm2 = 0.0
-        for t in range(total):
-            rec = st.reconstruct_slice(t)
-            err2 += torch.sum((rec.double() - data[t].double()) ** 2).item()
-            nrm2 += torch.sum(data[t].double() ** 2).item()
-        result["true_rel_error"] = math.sqrt(err2 / nrm2)
-        result["eps_met"] = result["true_rel_error"] <= w["tau"]
+    result.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
+    if not args.no_variants:
+        result["variants"] = {}
+        for prec in ("fp64", "bf16x3", "fp32"):
+            if prec == args.precision:
+                continue
+            info, vprof = run(prec, False)
+            vg, vroof = roofline(vprof, prec)
+            info["roofline"] = vroof
+            info["ttm_ms"] = round(vprof["ttm1"]["ms"] + vprof["ttm"]["ms"], 3)
+            result["variants"][prec] = info
     if not args.no_cpu_baseline:
         k = args.cpu_updates
         host = [data[t].cpu().numpy().astype(np.float64).reshape(stream.dims, order="F")
                 for t in range(n_init + k)]
         log(f"timing the FP64 oracle on {k} updates")
         result["cpu_baseline"] = cpu_baseline(host, n_init, w["tau"], k)
-    st.close()
     print(json.dumps(result), flush=True)
 
 

@@ -66,7 +66,8 @@ typedef struct st_config {
                                   Alg. 4 in which ||E_k|| is re-evaluated with FP64
                                   products; 0 = default (1e-2 FP32, 1e-1 bf16x3) */
   int64_t max_rank_d;          /* cap on the streaming rank r_d; 0 = no cap */
-  void *stream;                /* hipStream_t to run on; NULL = library-owned stream */
+  void *stream;                /* hipStream_t to run on; NULL = the default (null)
+                                  stream, which orders with all other work */
   int32_t profile;             /* nonzero: time every kernel group with HIP events */
 } st_config;
 
@@ -145,10 +146,11 @@ int st_ranks(const st_handle *h, int64_t *ranks, int64_t *n_d);
 int st_core(const st_handle *h, float *out, int64_t cap, int64_t *need, int where);
 
 /* The auxiliary tensor V of the core factorization C = V x_d S (Sec. 3.2,
- * Assumption 1(c)) as the column-major float32 matrix V_(d)^T of size
- * (r_1 ... r_{d-1}) x r_d, into out (host or device). out == NULL only sets
- * *need. Errors: ST_ESMALL, ST_ESTATE, ST_EINVAL. */
-int st_aux_v(const st_handle *h, float *out, int64_t cap, int64_t *need, int where);
+ * Assumption 1(c)) as the column-major float64 matrix V_(d)^T of size
+ * (r_1 ... r_{d-1}) x r_d, into out (host or device). V is held in FP64 in
+ * every precision form. out == NULL only sets *need.
+ * Errors: ST_ESMALL, ST_ESTATE, ST_EINVAL. */
+int st_aux_v(const st_handle *h, double *out, int64_t cap, int64_t *need, int where);
 
 /* Dense factor U_mode (mode 0..d-1; mode d-1 is the streaming factor of size
  * n_d x r_d), column-major float64, into out (host or device). out == NULL only
@@ -191,9 +193,10 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
  * (the residual of Alg. 4) when rows > 0, or E = X when rows == 0; A is a
  * rows x dims[mode] row-major float32 device matrix (may be NULL when rows == 0).
  * G is written to the host array g (dims[mode]^2 doubles, column-major).
- * gram_precision: 0 = FP32 products, 1 = bf16x3 products, 2 = FP64 products (the
- * residual is always formed with FP32 products). dims[mode] <= 512, rows <= 256.
- * Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
+ * gram_precision: 0 = FP32 products, 1 = bf16x3 products (the residual formed
+ * with FP32 products in both; dims[mode] <= 512), 2 = FP64 throughout (the
+ * residual formed with FP64 products and kept in FP64; dims[mode] <= 256).
+ * rows <= 256. Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
 int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
             int64_t rows, double *g, int32_t gram_precision, void *stream);
 

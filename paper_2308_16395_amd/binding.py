@@ -271,11 +271,11 @@ class StreamingTucker:
         return out
 
     def aux_v(self):
-        """V of C = V x_d S as a float32 device tensor of shape (r_1...r_{d-1}, r_d)."""
+        """V of C = V x_d S as a float64 device tensor of shape (r_1...r_{d-1}, r_d)."""
         t = self._torch
         need = C.c_int64()
         self._check(st_aux_v(self._h, None, 0, C.byref(need), ST_DEVICE))
-        out = t.empty(need.value, dtype=t.float32, device="cuda")
+        out = t.empty(need.value, dtype=t.float64, device="cuda")
         self._check(st_aux_v(self._h, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE))
         rd = self.ranks[-1]
         return out.reshape(rd, -1).T

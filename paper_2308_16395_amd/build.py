@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstucker.so")
-SOURCES = ["k_fiber.hip", "k_isvd.hip", "engine.hip"]
+SOURCES = ["k_fiber_ff.hip", "k_fiber_fd.hip", "k_fiber_dd.hip", "k_gram.hip", "k_rot.hip",
+           "k_isvd.hip", "engine.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 

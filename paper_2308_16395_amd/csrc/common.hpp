@@ -91,54 +91,65 @@ __host__ __device__ inline int64_t map_new_to_old(const RowMap &m, int64_t row) 
 //           element j sits at base + a*j. (a = 1: contiguous fibres.)
 //  MAPPED : fibre f starts at map(f) (or is all-zero if map(f) < 0); element
 //           j at base + a*j, and element j == n (one extra element) is taken
-//           from `extra[f]` when `extra` is not null.
+//           from `extra[f]` by the rotations.
+// The elements are FP32 (x64 = 0) or FP64 (x64 = 1).
 struct FiberIn {
-  const float *x;
+  const void *x;
+  int x64;
   int64_t a;        // element stride
   int64_t n;        // fibre length (without the extra element)
   int64_t F;        // number of fibres
   int mapped;       // 0: STRIDED, 1: MAPPED
   RowMap map;
-  const float *extra;  // MAPPED only: optional element n of every fibre
+  const double *extra;  // MAPPED only: optional element n of every fibre
 };
 
-// Output P[f][m] of a fibre contraction at (f % ao) + ao*m + ao*mo*(f / ao).
+// Output P[f][m] of a fibre contraction at (f % ao) + ao*m + ao*mo*(f / ao),
+// FP32 (o64 = 0) or FP64 (o64 = 1).
 struct FiberOut {
-  float *p;
+  void *p;
+  int o64;
   int64_t ao;
   int64_t mo;
 };
 
 // P[f][m] = sum_j X[f][j] * W[m][j] for m in [m0, m0 + mcount); W is row-major
-// with leading dimension ldw over j (K = n, or n + 1 with an extra element).
-// When `resid_partials` is not null (STRIDED only, m0 = 0, mcount = all rows of
-// W), also computes E = X - P x W^T per fibre and writes per-block FP64
-// partial sums {sum E^2, sum X^2} to resid_partials[2 * block].
-// `w_hi`/`w_lo` are the bf16 splits of W (row-major, ld = ldw_bf) for BF16X3.
+// with leading dimension ldw over j. When `resid_partials` is not null
+// (STRIDED only, m0 = 0, mcount = all rows of W), also computes
+// E = X - P x W^T per fibre and writes per-block FP64 partial sums
+// {sum E^2, sum X^2} to resid_partials[2 * block].
+// `w_hi`/`w_lo` are the bf16 splits of W (row-major, ld = ldw_bf) for BF16X3;
+// `w64` its FP64 form (ld = ldw) for Prec::FP64.
 struct FiberW {
   const float *w;
   int64_t ldw;
   const __bf16 *w_hi;
   const __bf16 *w_lo;
   int64_t ldw_bf;
-  const double *w64;  // FP64 copy of W (row-major, ld = ldw) for Prec::FP64
+  const double *w64;
 };
 
+// Input/output element types: FP32 -> FP32, FP32 -> FP64 and FP64 -> FP64.
 int fiber_blocks(int64_t F);
 hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int mcount,
                                 const FiberOut &out, double *resid_partials, Prec prec,
                                 hipStream_t s);
 
-// Same contraction for the mode-d rotations with an FP64 W (row-major, ld ldw)
-// and FP64 products and accumulation; output rounded to FP32 once.
-hipError_t launch_rot64(const FiberIn &in, const double *w, int64_t ldw, int m0, int mcount,
-                        const FiberOut &out, hipStream_t s);
+// Mode-d rotation (MAPPED input) with FP64 products and sums:
+// P[f][m] = sum_k X'[f][k] W[m][k] (W row-major, ld ldw), X'[f][k] = X[f][k]
+// for k < n; element n: none (extra_mode 0), extra[f] (1), or
+// extra[f] - sum_{k<n} X[f][k] pvec[k] formed in FP64 (2).
+// `w64` selects FP64 X, W and P; otherwise all three are FP32 (the output is
+// rounded once).
+hipError_t launch_rot64(const FiberIn &in, const void *w, int w64, int64_t ldw, int m0,
+                        int mcount, const FiberOut &out, int extra_mode, const double *pvec,
+                        hipStream_t s);
 
 // Gram of the residual E = X - (X x W^T) x W (or of X itself when rows == 0)
 // over all fibres: writes per-block partials of the lower-triangular 16x16
 // tiles; `gram_reduce` sums them in FP64 into G (n x n, column-major). The
 // residual is formed with FP64 products when `e64` (W.w64 must be set), else
-// with FP32 products; the Gram products use `gp`.
+// with FP32 products; the Gram products use `gp` (FP64: E kept in FP64).
 enum class GramPrec : int { FP32 = 0, BF16X3 = 1, FP64 = 2 };
 int gram_blocks(int64_t F);
 size_t gram_partial_elems(int64_t n, int nblocks);
@@ -149,5 +160,13 @@ hipError_t launch_gram_reduce(const double *partials, int nblocks, int64_t n, do
 
 // Sum `count` pairs of FP64 partials into out[0], out[1] (fixed order).
 hipError_t launch_reduce_pairs(const double *partials, int count, double *out, hipStream_t s);
+
+// Typed fibre launchers (one translation unit each).
+hipError_t launch_fiber_ff(const FiberIn &in, const FiberW &w, int m0, int mcount,
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s);
+hipError_t launch_fiber_fd(const FiberIn &in, const FiberW &w, int m0, int mcount,
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s);
+hipError_t launch_fiber_dd(const FiberIn &in, const FiberW &w, int m0, int mcount,
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s);
 
 }  // namespace st

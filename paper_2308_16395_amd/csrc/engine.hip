@@ -120,18 +120,21 @@ struct st_handle {
   DBuf<double> Ud[2];
   int64_t ud_ld[2] = {0, 0};
   DBuf<double> S[2];
-  DBuf<float> V[2], C[2];
+  DBuf<double> V[2];  // auxiliary matrix (FP64 in every form: it decides the ISVD test)
+  DBuf<float> C[2];   // core, mode-d unfolding transposed
   int cur = 0;
 
   // work buffers
-  DBuf<float> D[2], evec, wrow;
+  DBuf<double> D[2];   // partial cores D*_k of the update (FP64)
+  DBuf<float> RB[2], wrow;  // reconstruction work
   DBuf<double> part, sums;
   DBuf<double> gram_part;
   DBuf<double> G, eigval, eigwork, Wnew, coef;
   DBuf<int> info;
-  DBuf<double> colpart, q2part, p1, p2, p, p3;
+  DBuf<double> colpart, q2part, p1, p2, p;
   DBuf<double> U2, V2;
-  DBuf<double> Wv, Wc;
+  DBuf<double> Wv;
+  DBuf<float> Wc;
   // secular scratch
   DBuf<double> sd, sz, szh, smu, srot_cs, szz;
   DBuf<int> sact, sK, sdefl, sorg, srot_t, scounts;
@@ -387,8 +390,9 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
   int64_t rr[ST_MAX_MODES] = {};
   double tails = 0.0;
   std::vector<double> desc;
-  DBuf<float> T[2];
-  const float *Din = x0;
+  DBuf<double> T[2];
+  const void *Din = x0;
+  int din64 = 0;
   int sel = 0;
   int rc = ST_OK;
   for (int k = 0; k <= m && rc == ST_OK; ++k) {
@@ -397,6 +401,7 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
     const int64_t b = (k < m) ? nprod(k + 1) * n_init : 1;
     FiberIn in{};
     in.x = Din;
+    in.x64 = din64;
     in.a = a;
     in.n = nk;
     in.F = a * b;
@@ -428,13 +433,14 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
         rc = hipfail(e, "init partial core");
         break;
       }
-      FiberOut out{T[sel].p, a, rk};
+      FiberOut out{T[sel].p, 1, a, rk};
       e = launch_fiber_project(in, wmat(k), 0, (int)rk, out, nullptr, prec, stream);
       if (e != hipSuccess) {
         rc = hipfail(e, "init projection");
         break;
       }
       Din = T[sel].p;
+      din64 = 1;
       sel ^= 1;
     } else {
       const int64_t R = a;
@@ -461,9 +467,10 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
       if (e == hipSuccess) e = V[cur].ensure((size_t)(R * rk));
       if (e == hipSuccess) e = C[cur].ensure((size_t)(R * rk));
       // V = A^T U_d S^-1 and C_(d)^T = A^T U_d, A = C*_{d-1,(d)} (FP64 accumulation)
+      if (e == hipSuccess && !din64) e = hipErrorInvalidValue;  // d >= 2: A is a partial core
       if (e == hipSuccess)
-        e = launch_init_vc(Din, R, n_init, Ud[cur].p, ldu, (int)rk, S[cur].p, V[cur].p, C[cur].p,
-                           stream);
+        e = launch_init_vc(static_cast<const double *>(Din), R, n_init, Ud[cur].p, ldu, (int)rk,
+                           S[cur].p, V[cur].p, C[cur].p, stream);
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (e != hipSuccess) {
         rc = hipfail(e, "init core");
@@ -505,7 +512,8 @@ int st_handle::do_update(const float *y) {
   if (e != hipSuccess) return hipfail(e, "pinned buffer");
 
   std::vector<double> desc;
-  const float *Din = y;
+  const void *Din = y;
+  int din64 = 0;
   int dsel = 0;
   double delta2 = 0.0, eps = 0.0, ynorm2 = 0.0;
   int rc;
@@ -515,12 +523,13 @@ int st_handle::do_update(const float *y) {
     const int64_t b = nprod(k + 1);
     FiberIn in{};
     in.x = Din;
+    in.x64 = din64;
     in.a = a;
     in.n = nk;
     in.F = a * b;
-    float *Dout = D[dsel].p;
+    double *Dout = D[dsel].p;
     const int tgroup = k == 0 ? ST_K_TTM1 : ST_K_TTM;
-    rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, a, r[k]}, prec, tgroup);
+    rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, 1, a, r[k]}, prec, tgroup);
     if (rc != ST_OK) return rc;
     double e2 = hpin[0];
     if (k == 0) {
@@ -531,7 +540,7 @@ int st_handle::do_update(const float *y) {
     if (!std::isfinite(e2)) return fail(ST_ENONFINITE, "non-finite residual in mode %d", k + 1);
     if (prec != Prec::FP64 && std::fabs(std::sqrt(e2) - eps) <= guard_rel * eps) {
       // close to the threshold: decide with the FP64 products
-      rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, a, r[k]}, Prec::FP64, tgroup);
+      rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, 1, a, r[k]}, Prec::FP64, tgroup);
       if (rc != ST_OK) return rc;
       e2 = hpin[0];
       ++stt.guard_hits;
@@ -540,6 +549,7 @@ int st_handle::do_update(const float *y) {
     if (std::sqrt(e2) <= eps) {  // Alg. 4: keep U_k, D*_k = P_k
       delta2 += e2;
       Din = Dout;
+      din64 = 1;
       dsel ^= 1;
       continue;
     }
@@ -556,6 +566,7 @@ int st_handle::do_update(const float *y) {
     if (rp <= 0) {  // the Gram resolves nothing above the tolerance
       delta2 += e2;
       Din = Dout;
+      din64 = 1;
       dsel ^= 1;
       continue;
     }
@@ -568,11 +579,13 @@ int st_handle::do_update(const float *y) {
     stt.grew[k] = (int32_t)rp;
     // D*_k = D*_{k-1} x_k [U_k W_k]^T
     tic();
-    e = launch_fiber_project(in, wmat(k), 0, (int)rn[k], FiberOut{Dout, a, rn[k]}, nullptr, prec,
-                             stream);
-    toc(ST_K_TTM_EXT, 2.0 * in.F * nk * rn[k], 4.0 * in.F * (nk + rn[k]));
+    e = launch_fiber_project(in, wmat(k), 0, (int)rn[k], FiberOut{Dout, 1, a, rn[k]}, nullptr,
+                             prec, stream);
+    toc(ST_K_TTM_EXT, 2.0 * in.F * nk * rn[k],
+        (din64 ? 8.0 : 4.0) * in.F * nk + 8.0 * in.F * rn[k]);
     if (e != hipSuccess) return hipfail(e, "extended projection");
     Din = Dout;
+    din64 = 1;
     dsel ^= 1;
   }
   const double ms_modes = ms_since(t0);
@@ -587,7 +600,8 @@ int st_handle::do_update(const float *y) {
     map.r_new[k] = (int32_t)rn[k];
     if (rn[k] != r[k]) map.identity = 0;
   }
-  const float *dvec = Din;
+  if (!din64) return fail(ST_EINVAL, "slice has no slice modes");
+  const double *dvec = static_cast<const double *>(Din);
   const int rdi = (int)rd;
   const int nb = isvd_blocks(Rnew);
   e = colpart.ensure((size_t)nb * rdi);
@@ -595,8 +609,7 @@ int st_handle::do_update(const float *y) {
   if (e == hipSuccess) e = p1.ensure(rdi);
   if (e == hipSuccess) e = p2.ensure(rdi);
   if (e == hipSuccess) e = p.ensure(rdi);
-  if (e == hipSuccess) e = p3.ensure(rdi);
-  if (e == hipSuccess) e = evec.ensure(Rnew);
+
   if (e != hipSuccess) return hipfail(e, "isvd buffers");
   IsvdArgs ia{};
   ia.V = V[cur].p;
@@ -606,46 +619,47 @@ int st_handle::do_update(const float *y) {
   ia.map = map;
   ia.d = dvec;
   ia.p1 = p1.p;
-  ia.p2 = p2.p;
-  ia.e = evec.p;
   ia.colpart = colpart.p;
   ia.q2part = q2part.p;
   tic();
+  // p1 = V^T d; e1 = d - V p1, ||e1||^2, p2 = V^T e1; p = p1 + p2
   e = launch_isvd_pass(1, ia, nb, stream);
   if (e == hipSuccess)
     e = launch_colsum(colpart.p, nb, rdi, p1.p, nullptr, nullptr, nullptr, nullptr, stream);
   if (e == hipSuccess) e = launch_isvd_pass(2, ia, nb, stream);
   if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nb, rdi, p2.p, p1.p, p.p, nullptr, nullptr, stream);
-  if (e == hipSuccess) e = launch_isvd_pass(3, ia, nb, stream);
-  if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nb, rdi, p3.p, nullptr, nullptr, q2part.p, sums.p, stream);
-  // p1 = V^T d; e1 = d - V p1, p2 = V^T e1; e = e1 - V p2, V^T e: 10 R r flops, V read 3x
-  toc(ST_K_ISVD, 10.0 * Rnew * rdi, 3.0 * 4.0 * Rold * rdi + 4.0 * 4.0 * Rnew);
+    e = launch_colsum(colpart.p, nb, rdi, p2.p, p1.p, p.p, q2part.p, sums.p, stream);
+  // 4 R r flops (two passes of V^T x) + 2 R r (row dots); V (FP64) read twice, d twice
+  toc(ST_K_ISVD, 6.0 * Rnew * rdi, 2.0 * 8.0 * Rold * rdi + 2.0 * 8.0 * Rnew);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hpin, sums.p, sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hpin + 1, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 1 + rdi, p3.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
+    e = hipMemcpyAsync(hpin + 1 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
                        stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "isvd projections");
   settle();
-  const double q2 = hpin[0];
-  const double q = std::sqrt(std::max(q2, 0.0));
-  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
-  double pmax = 0.0, p3max = 0.0;
+  // q^2 = ||e1 - V p2||^2 = ||e1||^2 - ||p2||^2 (V orthonormal; p2 ~ u ||d||)
+  const double e1sq = hpin[0];
+  double pmax = 0.0, p2max = 0.0, p2sq = 0.0;
   for (int j = 0; j < rdi; ++j) {
     pmax = std::max(pmax, std::fabs(hpin[1 + j]));
-    p3max = std::max(p3max, std::fabs(hpin[1 + rdi + j]));
+    const double v2 = hpin[1 + rdi + j];
+    p2max = std::max(p2max, std::fabs(v2));
+    p2sq += v2 * v2;
   }
+  const double q2 = std::max(e1sq - p2sq, 0.0);
+  const double q = std::sqrt(q2);
+  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
   const double tol = 8.0 * 0x1p-53 * std::max({S_host.empty() ? 0.0 : S_host[0], pmax, q});
   const int grow = (q > eps && q > tol) ? 1 : 0;
   const int64_t c = rd + grow;
   stt.q = q;
   stt.isvd_ignored = grow ? 0 : 1;
-  stt.orth_check = q > 0.0 ? p3max / q : 0.0;
+  // the check of Alg. 3 on the single-pass complement: max_j |V(:,j)^T e1| / ||e1||
+  stt.orth_check = e1sq > 0.0 ? p2max / std::sqrt(e1sq) : 0.0;
   stt.qr_fired = (grow && stt.orth_check > orth_tol) ? 1 : 0;
   if (max_rank_d > 0 && c > max_rank_d)
     return fail(ST_ECAPACITY, "streaming rank %lld exceeds the cap", (long long)c);
@@ -682,26 +696,32 @@ int st_handle::do_update(const float *y) {
   // V~ = [V v] V''  (mode-d TTM of V with the padded rows mapped)
   FiberIn vin{};
   vin.x = V[cur].p;
+  vin.x64 = 1;
   vin.a = Rold;
   vin.n = rd;
   vin.F = Rnew;
   vin.mapped = 1;
   vin.map = map;
-  vin.extra = grow ? evec.p : nullptr;
+  vin.extra = grow ? dvec : nullptr;
   tic();
-  e = launch_rot64(vin, Wv.p, ldwv, 0, (int)c, FiberOut{V[nxt].p, Rnew, c}, stream);
-  // read V (R_old x r_d) and e, write V~ (R_new x c): 2 R_new K c flops
-  toc(ST_K_ROT_V, 2.0 * Rnew * (double)kv * c,
-      4.0 * ((double)Rold * rd + (grow ? Rnew : 0) + (double)Rnew * c));
+  // V~ = [V v] V'' with v = e / q, e = d - V p formed per row in FP64
+  e = launch_rot64(vin, Wv.p, 1, ldwv, 0, (int)c, FiberOut{V[nxt].p, 1, Rnew, c}, grow ? 2 : 0,
+                   p.p, stream);
+  // read V (R_old x r_d, FP64) and d, write V~ (R_new x c, FP64): 2 R_new K c flops
+  toc(ST_K_ROT_V, 2.0 * Rnew * (double)kv * c + (grow ? 2.0 * Rnew * rd : 0.0),
+      8.0 * ((double)Rold * rd + (grow ? Rnew : 0) + (double)Rnew * c));
   if (e != hipSuccess) return hipfail(e, "V rotation");
   // C~_(d) = U~_d(1:n_d,:)^T U_d C_(d) + U~_d(n_d+1,:)^T d^T = U''^T [C_(d); d^T]
   FiberIn cin = vin;
   cin.x = C[cur].p;
+  cin.x64 = 0;
   cin.extra = dvec;
   tic();
-  e = launch_rot64(cin, Wc.p, ldwc, 0, (int)c, FiberOut{C[nxt].p, Rnew, c}, stream);
+  e = launch_rot64(cin, Wc.p, 0, ldwc, 0, (int)c, FiberOut{C[nxt].p, 0, Rnew, c}, 1, nullptr,
+                   stream);
+  // read C (FP32) and d (FP64), write C~ (FP32)
   toc(ST_K_ROT_C, 2.0 * Rnew * (double)(rd + 1) * c,
-      4.0 * ((double)Rold * rd + Rnew + (double)Rnew * c));
+      4.0 * ((double)Rold * rd + (double)Rnew * c) + 8.0 * Rnew);
   if (e != hipSuccess) return hipfail(e, "core rotation");
   tic();
   e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
@@ -740,8 +760,8 @@ int st_handle::do_reconstruct_slice(int64_t t, float *out) {
   if (t < 0 || t >= nd || out == nullptr) return fail(ST_EINVAL, "slice index out of range");
   const int64_t R = rprod(r, m);
   hipError_t e = wrow.ensure(round_up(rd, 4));
-  if (e == hipSuccess) e = D[0].ensure(NY);
-  if (e == hipSuccess) e = D[1].ensure(NY);
+  if (e == hipSuccess) e = RB[0].ensure(NY);
+  if (e == hipSuccess) e = RB[1].ensure(NY);
   if (e != hipSuccess) return hipfail(e, "reconstruct buffers");
   e = launch_ud_row(Ud[cur].p, ud_ld[cur], t, (int)rd, wrow.p, stream);
   FiberIn in{};
@@ -752,9 +772,10 @@ int st_handle::do_reconstruct_slice(int64_t t, float *out) {
   FiberW w{};
   w.w = wrow.p;
   w.ldw = rd;
-  float *cur_buf = (m == 0) ? out : D[0].p;
+  float *cur_buf = (m == 0) ? out : RB[0].p;
   if (e == hipSuccess)
-    e = launch_fiber_project(in, w, 0, 1, FiberOut{cur_buf, R, 1}, nullptr, Prec::FP32, stream);
+    e = launch_fiber_project(in, w, 0, 1, FiberOut{cur_buf, 0, R, 1}, nullptr, Prec::FP32,
+                             stream);
   int sel = 1;
   int64_t shape[ST_MAX_MODES];
   for (int k = 0; k < m; ++k) shape[k] = r[k];
@@ -770,9 +791,9 @@ int st_handle::do_reconstruct_slice(int64_t t, float *out) {
     FiberW uw{};
     uw.w = Ut[k];
     uw.ldw = n[k];
-    float *dst = (k == 0) ? out : D[sel].p;
-    e = launch_fiber_project(ein, uw, 0, (int)n[k], FiberOut{dst, a, n[k]}, nullptr, Prec::FP32,
-                             stream);
+    float *dst = (k == 0) ? out : RB[sel].p;
+    e = launch_fiber_project(ein, uw, 0, (int)n[k], FiberOut{dst, 0, a, n[k]}, nullptr,
+                             Prec::FP32, stream);
     shape[k] = n[k];
     cur_buf = dst;
     sel ^= 1;
@@ -798,8 +819,8 @@ void st_handle::destroy() {
     V[i].release();
     C[i].release();
     D[i].release();
+    RB[i].release();
   }
-  evec.release();
   wrow.release();
   part.release();
   sums.release();
@@ -815,7 +836,6 @@ void st_handle::destroy() {
   p1.release();
   p2.release();
   p.release();
-  p3.release();
   U2.release();
   V2.release();
   Wv.release();
@@ -893,14 +913,10 @@ int st_create(const st_config *cfg, st_handle **out) {
   h->max_rank_d = cfg->max_rank_d;
   h->profile = cfg->profile != 0;
   hipError_t e = hipGetDevice(&h->device);
-  if (e == hipSuccess) {
-    if (cfg->stream) {
-      h->stream = (hipStream_t)cfg->stream;
-    } else {
-      e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
-      h->own_stream = (e == hipSuccess);
-    }
-  }
+  // the caller's stream, or the null stream (never a private non-blocking one:
+  // inputs produced on the default stream must be complete before we read them)
+  h->stream = (hipStream_t)cfg->stream;
+  h->own_stream = false;
   for (int k = 0; k < h->m && e == hipSuccess; ++k) {
     const int64_t nk = h->n[k];
     h->ldb[k] = round_up(nk, 8);
@@ -976,7 +992,7 @@ int st_core(const st_handle *hc, float *out, int64_t cap, int64_t *need, int whe
   return ST_OK;
 }
 
-int st_aux_v(const st_handle *hc, float *out, int64_t cap, int64_t *need, int where) {
+int st_aux_v(const st_handle *hc, double *out, int64_t cap, int64_t *need, int where) {
   st_handle *h = const_cast<st_handle *>(hc);
   if (!h) return ST_EINVAL;
   if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
@@ -985,7 +1001,7 @@ int st_aux_v(const st_handle *hc, float *out, int64_t cap, int64_t *need, int wh
   if (!out) return ST_OK;
   if (cap < cnt) return h->fail(ST_ESMALL, "buffer too small");
   (void)hipSetDevice(h->device);
-  hipError_t e = hipMemcpyAsync(out, h->V[h->cur].p, cnt * sizeof(float),
+  hipError_t e = hipMemcpyAsync(out, h->V[h->cur].p, cnt * sizeof(double),
                                 where == ST_DEVICE ? hipMemcpyDeviceToDevice
                                                    : hipMemcpyDeviceToHost,
                                 h->stream);
@@ -1098,7 +1114,7 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
     if (e == hipSuccess) e = hipMalloc((void **)&sum, 2 * sizeof(double));
   }
   if (e == hipSuccess)
-    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, lo, rows}, part, pr, s);
+    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, 0, lo, rows}, part, pr, s);
   if (e == hipSuccess && norms) e = launch_reduce_pairs(part, nb, sum, s);
   if (e == hipSuccess && norms)
     e = hipMemcpyAsync(norms, sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1124,7 +1140,7 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
     if (k > mode) hi *= dims[k];
   }
   const int64_t nk = dims[mode];
-  if (nk > 512 || rows > nk) return ST_EINVAL;
+  if (nk > (gram_precision == 2 ? 256 : 512) || rows > nk) return ST_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   FiberIn in{};
   in.x = x;
@@ -1135,16 +1151,24 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
   w.w = a;
   w.ldw = nk;
   const int nb = gram_blocks(in.F);
-  double *part = nullptr, *G = nullptr;
+  double *part = nullptr, *G = nullptr, *a64 = nullptr;
+  // the FP64 Gram also forms the residual with FP64 products
+  const bool e64 = gram_precision == 2 && rows > 0;
   hipError_t e = hipMalloc((void **)&part, gram_partial_elems(nk, nb) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void **)&G, nk * nk * sizeof(double));
+  if (e == hipSuccess && e64) {
+    e = hipMalloc((void **)&a64, rows * nk * sizeof(double));
+    if (e == hipSuccess) e = launch_f32_to_f64(a, rows * nk, a64, s);
+    w.w64 = a64;
+  }
   if (e == hipSuccess)
-    e = launch_gram(in, w, (int)rows, part, nb, (GramPrec)gram_precision, false, s);
+    e = launch_gram(in, w, (int)rows, part, nb, (GramPrec)gram_precision, e64, s);
   if (e == hipSuccess) e = launch_gram_reduce(part, nb, nk, G, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g, G, nk * nk * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (part) (void)hipFree(part);
   if (G) (void)hipFree(G);
+  if (a64) (void)hipFree(a64);
   if (e == hipErrorOutOfMemory) return ST_ENOMEM;
   return e == hipSuccess ? ST_OK : ST_EHIP;
 }

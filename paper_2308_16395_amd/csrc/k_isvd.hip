@@ -7,108 +7,92 @@
 namespace st {
 
 // ---------------------------------------------------------------------------
-// CGS2 passes over V (Alg. 3, first lines, with a second Gram-Schmidt pass).
+// Gram-Schmidt passes over V (Alg. 3, first lines, done twice).
 //
-// V is the old auxiliary matrix (rows at the old ranks, leading dimension ldv,
-// r columns); d, e are vectors at the new ranks; rows are mapped new -> old.
-// Each block stages a tile of TR rows x r columns of V in LDS with coalesced
-// loads, then
+// V is the old auxiliary matrix (FP64; rows at the old ranks, leading
+// dimension ldv, r columns); d is the FP64 slice projection at the new ranks;
+// rows are mapped new -> old (padded rows of V are zero). Each block stages
+// tiles of TR rows x r columns of V in LDS with coalesced (vector when
+// possible) loads, then
 //   PASS 1: colpart += V^T d
-//   PASS 2: e1 = d - V p1 (row dots), colpart += V^T e1
-//   PASS 3: e = (d - V p1) - V p2, store e, q2 += e^2, colpart += V^T e
-// so that V is read from HBM once per pass.
+//   PASS 2: e1 = d - V p1 (FP64 row dots), q2part += ||e1||^2, colpart += V^T e1
+// so V is read from HBM once per pass. The second correction p2 = V^T e1 and
+// q^2 = ||e1||^2 - ||p2||^2 complete the two-pass projection; the complement
+// e = d - V (p1 + p2) itself is formed inside the V rotation.
 // ---------------------------------------------------------------------------
-template <int PASS>
+template <int PASS, int TR>
 __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
   extern __shared__ double sh[];
-  const int TR = a.tile_rows;
+  constexpr int LDT = TR + 1;
   const int r = a.r;
   const int tid = threadIdx.x;
-  double *p1s = sh;                    // [r]
-  double *p2s = p1s + r;               // [r]
-  double *ev = p2s + r;                // [TR]
-  double *rowred = ev + TR;            // [256] = [threads per row][TR]
-  int64_t *orow = reinterpret_cast<int64_t *>(rowred + 256);     // [TR]
-  float *tile = reinterpret_cast<float *>(orow + TR);            // [r][TR+1]
-  const int ldt = TR + 1;
-
-  if (PASS >= 2)
+  double *p1s = sh;                   // [r]
+  double *ev = p1s + r;               // [TR]
+  double *rowred = ev + TR;           // [256 / TR][TR]
+  int64_t *orow = reinterpret_cast<int64_t *>(rowred + 256);  // [TR]
+  double *tile = reinterpret_cast<double *>(orow + TR);          // [r][LDT]
+  if (PASS == 2)
     for (int j = tid; j < r; j += blockDim.x) p1s[j] = a.p1[j];
-  if (PASS >= 3)
-    for (int j = tid; j < r; j += blockDim.x) p2s[j] = a.p2[j];
 
   constexpr int kMaxCols = 8;  // r <= 2048
   double colacc[kMaxCols];
 #pragma unroll
   for (int q = 0; q < kMaxCols; ++q) colacc[q] = 0.0;
   double q2 = 0.0;
+  const bool vec = a.map.identity && (a.ldv & 1) == 0;
 
   const int64_t ntiles = (a.R + TR - 1) / TR;
-  const int tpr = blockDim.x / TR;  // threads per row in the row phase
   for (int64_t tile_i = blockIdx.x; tile_i < ntiles; tile_i += gridDim.x) {
     const int64_t row0 = tile_i * TR;
     __syncthreads();
-    if (tid < TR) {
-      const int64_t row = row0 + tid;
-      orow[tid] = row < a.R ? map_new_to_old(a.map, row) : -1;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < r * TR; idx += blockDim.x) {
-      const int j = idx / TR, i = idx - j * TR;
-      const int64_t o = orow[i];
-      tile[j * ldt + i] = (o >= 0) ? a.V[o + a.ldv * (int64_t)j] : 0.0f;
+    if (vec && row0 + TR <= a.R) {
+      // thread t: rows 2 (t % (TR/2)) .. +1 of columns t / (TR/2) + (512/TR) it
+      constexpr int TPC = TR / 2, CPI = 256 / TPC;
+      const int rq = (tid % TPC) * 2;
+      for (int j = tid / TPC; j < r; j += CPI) {
+        const double2 v2 =
+            *reinterpret_cast<const double2 *>(a.V + row0 + rq + a.ldv * (int64_t)j);
+        double *t = tile + j * LDT + rq;
+        t[0] = v2.x;
+        t[1] = v2.y;
+      }
+    } else {
+      if (tid < TR) {
+        const int64_t row = row0 + tid;
+        orow[tid] = row < a.R ? map_new_to_old(a.map, row) : -1;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < r * TR; idx += blockDim.x) {
+        const int j = idx / TR, i = idx - j * TR;
+        const int64_t o = orow[i];
+        tile[j * LDT + i] = (o >= 0) ? a.V[o + a.ldv * (int64_t)j] : 0.0;
+      }
     }
     __syncthreads();
     // row phase
     if (PASS == 1) {
       if (tid < TR) {
         const int64_t row = row0 + tid;
-        ev[tid] = row < a.R ? (double)a.d[row] : 0.0;
+        ev[tid] = row < a.R ? a.d[row] : 0.0;
       }
     } else {
+      // TR == 64: 4 partial dots per row; TR == 32: 8
+      constexpr int SUB = 256 / TR;
       const int i = tid % TR, sub = tid / TR;
-      double s1 = 0.0, s2 = 0.0;
-      if (sub < tpr) {
-        for (int j = sub; j < r; j += tpr) {
-          const double vj = (double)tile[j * ldt + i];
-          s1 += vj * p1s[j];
-          if (PASS == 3) s2 += vj * p2s[j];
-        }
-      }
-      if (sub < tpr) rowred[sub * TR + i] = s1;
+      double s1 = 0.0;
+      for (int j = sub; j < r; j += SUB) s1 += tile[j * LDT + i] * p1s[j];
+      rowred[sub * TR + i] = s1;
       __syncthreads();
-      if (tid < TR) {
-        double t1 = 0.0;
-        for (int q = 0; q < tpr; ++q) t1 += rowred[q * TR + tid];
-        rowred[tid] = t1;  // reuse slot 0 after everyone summed (see sync below)
-      }
-      __syncthreads();
-      double dot1 = (tid < TR) ? rowred[tid] : 0.0;
-      __syncthreads();
-      if (PASS == 3) {
-        if (sub < tpr) rowred[sub * TR + i] = s2;
-        __syncthreads();
-        if (tid < TR) {
-          double t2 = 0.0;
-          for (int q = 0; q < tpr; ++q) t2 += rowred[q * TR + tid];
-          rowred[tid] = t2;
-        }
-        __syncthreads();
-      }
       if (tid < TR) {
         const int64_t row = row0 + tid;
-        double val = 0.0;
+        double e1 = 0.0;
         if (row < a.R) {
-          const double e1 = (double)a.d[row] - dot1;
-          if (PASS == 2) {
-            val = e1;
-          } else {
-            val = e1 - rowred[tid];
-            a.e[row] = (float)val;
-            q2 += val * val;
-          }
+          double dot = 0.0;
+          for (int q = 0; q < SUB; ++q) dot += rowred[q * TR + tid];
+          e1 = a.d[row] - dot;
         }
-        ev[tid] = val;
+        ev[tid] = e1;
+        q2 += e1 * e1;
       }
     }
     __syncthreads();
@@ -117,10 +101,11 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
     for (int q = 0; q < kMaxCols; ++q) {
       const int j = tid + q * blockDim.x;
       if (j < r) {
-        double s = 0.0;
-        const float *tr = tile + j * ldt;
-        for (int i = 0; i < TR; ++i) s += (double)tr[i] * ev[i];
-        colacc[q] += s;
+        double acc = 0.0;
+        const double *tr = tile + j * LDT;
+#pragma unroll 8
+        for (int i = 0; i < TR; ++i) acc += tr[i] * ev[i];
+        colacc[q] += acc;
       }
     }
   }
@@ -130,7 +115,7 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
     const int j = tid + q * blockDim.x;
     if (j < r) a.colpart[(size_t)j * gridDim.x + blockIdx.x] = colacc[q];
   }
-  if (PASS == 3) {
+  if (PASS == 2) {
     __shared__ double red[16];
     const double t = block_sum(q2, red);
     if (tid == 0) a.q2part[blockIdx.x] = t;
@@ -159,36 +144,36 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double *part, int nb,
 }
 
 int isvd_blocks(int64_t R) {
-  const int64_t t = (R + 31) / 32;
-  return (int)(t < 1024 ? (t > 0 ? t : 1) : 1024);
+  const int64_t t = (R + 63) / 64;
+  return (int)(t < 2048 ? (t > 0 ? t : 1) : 2048);
 }
 
-static size_t isvd_lds(int r, int TR) {
-  return sizeof(double) * (2 * (size_t)r + TR + 256) + sizeof(int64_t) * TR +
-         sizeof(float) * (size_t)r * (TR + 1);
+// rowred holds 256 doubles for either tile height
+static size_t isvd_lds(int r, int tr) {
+  return sizeof(double) * ((size_t)r + tr + 256) + sizeof(int64_t) * tr +
+         sizeof(double) * (size_t)r * (tr + 1);
+}
+
+static constexpr size_t kIsvdMaxLds = 160 * 1024;
+
+template <int PASS, int TR>
+static hipError_t launch_isvd_tr(const IsvdArgs &a, int nblocks, hipStream_t s) {
+  const size_t lds = isvd_lds(a.r, TR);
+  const void *fn = (const void *)isvd_pass_kernel<PASS, TR>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((isvd_pass_kernel<PASS, TR>), dim3(nblocks), dim3(256), lds, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s) {
-  if (a.r > 8 * 256) return hipErrorInvalidValue;
-  int TR = 32;
-  while (TR > 4 && isvd_lds(a.r, TR) > 150 * 1024) TR /= 2;
-  a.tile_rows = TR;
-  const size_t lds = isvd_lds(a.r, TR);
-  if (lds > 150 * 1024) return hipErrorInvalidValue;
-  if (pass == 1) {
-    hipFuncSetAttribute((const void *)isvd_pass_kernel<1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(isvd_pass_kernel<1>, dim3(nblocks), dim3(256), lds, s, a);
-  } else if (pass == 2) {
-    hipFuncSetAttribute((const void *)isvd_pass_kernel<2>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(isvd_pass_kernel<2>, dim3(nblocks), dim3(256), lds, s, a);
-  } else {
-    hipFuncSetAttribute((const void *)isvd_pass_kernel<3>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(isvd_pass_kernel<3>, dim3(nblocks), dim3(256), lds, s, a);
-  }
-  return hipGetLastError();
+  if (a.r > 8 * 256 || pass < 1 || pass > 2) return hipErrorInvalidValue;
+  // 64-row tiles while they fit in LDS, else 32-row tiles
+  const bool tall = isvd_lds(a.r, 64) <= kIsvdMaxLds;
+  if (!tall && isvd_lds(a.r, 32) > kIsvdMaxLds) return hipErrorInvalidValue;
+  if (pass == 1)
+    return tall ? launch_isvd_tr<1, 64>(a, nblocks, s) : launch_isvd_tr<1, 32>(a, nblocks, s);
+  return tall ? launch_isvd_tr<2, 64>(a, nblocks, s) : launch_isvd_tr<2, 32>(a, nblocks, s);
 }
 
 hipError_t launch_colsum(const double *part, int nb, int r, double *out, const double *add,
@@ -329,22 +314,23 @@ hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, co
   return hipGetLastError();
 }
 
-// Row-major FP64 rotation matrices for the mode-d TTMs of V and C:
+// Row-major FP32 rotation matrices for the mode-d TTMs of V and C:
 //   Wv[m][k] = V''[k][m] (k < kv), with row r scaled by 1/q when e is kept;
 //   Wc[m][k] = U''[k][m] (k <= r).
 __global__ void build_rot_w_kernel(const double *U2, const double *V2, int r, int c, int kv,
-                                   double inv_q, double *Wv, int64_t ldv, double *Wc, int64_t ldc) {
+                                   double inv_q, double *Wv, int64_t ldv, float *Wc,
+                                   int64_t ldc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)c * (r + 1);
   if (idx >= total) return;
   const int m = (int)(idx / (r + 1)), k = (int)(idx % (r + 1));
   const size_t src = (size_t)k + (size_t)(r + 1) * m;
-  Wc[m * ldc + k] = U2[src];
+  Wc[m * ldc + k] = (float)U2[src];
   if (k < kv) Wv[m * ldv + k] = (k == r) ? V2[src] * inv_q : V2[src];
 }
 
 hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
-                              double inv_q, double *Wv, int64_t ldv, double *Wc, int64_t ldc,
+                              double inv_q, double *Wv, int64_t ldv, float *Wc, int64_t ldc,
                               hipStream_t s) {
   const int64_t total = (int64_t)c * (r + 1);
   hipLaunchKernelGGL(build_rot_w_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
@@ -352,24 +338,26 @@ hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, 
   return hipGetLastError();
 }
 
-// Init: C^T = A U_d and V = A U_d S^-1 with A the (R x n_init) mode-d unfolding
-// of the last partial core, accumulated in FP64. With FP32 products the columns
-// of small singular value would carry a relative error of about u s_1 / s_k and
-// V would not be orthonormal to the accuracy the ISVD residual test needs.
-__global__ void init_vc_kernel(const float *A, int64_t R, int64_t nd, const double *Ud,
-                               int64_t ldu, int rd, const double *S, float *V, float *Cc) {
+// Init: C^T = A U_d and V = A U_d S^-1 with A the (R x n_init) FP64 mode-d
+// unfolding of the last partial core, accumulated in FP64. With FP32 products
+// the columns of small singular value would carry a relative error of about
+// u s_1 / s_k and V would not be orthonormal to the accuracy the ISVD residual
+// test needs.
+__global__ void init_vc_kernel(const double *A, int64_t R, int64_t nd, const double *Ud,
+                               int64_t ldu, int rd, const double *S, double *V, float *Cc) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= R) return;
   for (int m = 0; m < rd; ++m) {
     double acc = 0.0;
-    for (int64_t j = 0; j < nd; ++j) acc += (double)A[row + R * j] * Ud[j + ldu * m];
+    for (int64_t j = 0; j < nd; ++j) acc += A[row + R * j] * Ud[j + ldu * m];
     Cc[row + R * m] = (float)acc;
-    V[row + R * m] = (float)(acc / S[m]);
+    V[row + R * m] = acc / S[m];
   }
 }
 
-hipError_t launch_init_vc(const float *A, int64_t R, int64_t nd, const double *Ud, int64_t ldu,
-                          int rd, const double *S, float *V, float *Cc, hipStream_t s) {
+hipError_t launch_init_vc(const double *A, int64_t R, int64_t nd, const double *Ud,
+                          int64_t ldu, int rd, const double *S, double *V, float *Cc,
+                          hipStream_t s) {
   hipLaunchKernelGGL(init_vc_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, A, R, nd,
                      Ud, ldu, rd, S, V, Cc);
   return hipGetLastError();

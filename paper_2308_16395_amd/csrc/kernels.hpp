@@ -7,18 +7,15 @@
 namespace st {
 
 struct IsvdArgs {
-  const float *V;      // old V (or any old mode-d matrix), column-major
+  const double *V;     // old V, column-major
   int64_t ldv;         // its leading dimension (old row count)
   int r;               // columns
   int64_t R;           // rows at the new ranks
   RowMap map;          // new row -> old row
-  const float *d;      // [R] new slice projection
-  const double *p1;    // [r]
-  const double *p2;    // [r]
-  float *e;            // [R] output of pass 3
-  double *colpart;     // [nblocks * r]
-  double *q2part;      // [nblocks]
-  int tile_rows;       // set by the launcher
+  const double *d;     // [R] new slice projection
+  const double *p1;    // [r] (pass 2)
+  double *colpart;     // [r * nblocks], column-major
+  double *q2part;      // [nblocks] (pass 2)
 };
 
 int isvd_blocks(int64_t R);
@@ -31,10 +28,11 @@ hipError_t launch_secular_svd(SecData s, const double *S, const double *p, doubl
 hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, const double *U2,
                             int c, double *Un, int64_t ldn, hipStream_t s);
 hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
-                              double inv_q, double *Wv, int64_t ldv, double *Wc, int64_t ldc,
+                              double inv_q, double *Wv, int64_t ldv, float *Wc, int64_t ldc,
                               hipStream_t s);
-hipError_t launch_init_vc(const float *A, int64_t R, int64_t nd, const double *Ud, int64_t ldu,
-                          int rd, const double *S, float *V, float *Cc, hipStream_t s);
+hipError_t launch_init_vc(const double *A, int64_t R, int64_t nd, const double *Ud,
+                          int64_t ldu, int rd, const double *S, double *V, float *Cc,
+                          hipStream_t s);
 hipError_t launch_new_columns(const double *Q, int64_t n, const double *U, int r, int k,
                               double *W, double *coef, hipStream_t s);
 hipError_t launch_append_cols(const double *W, int64_t n, int c0, int k, double *U64, float *Uf,
