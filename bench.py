@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (a known-size "
+                         "kernel against which HBM byte counters are calibrated)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the streaming update is sequential along the "
@@ -119,6 +122,14 @@ def main():
         raise SystemExit(f"warmup + steps exceed the {w['n_slices'] - n_init} updates of the stream")
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written by one copy kernel")
+        del src, dst
     stream = BlobStream(w["space"], w["n_vars"], w["n_blobs"], n_slices=w["n_slices"],
                         seed=w["seed"])
     ny = math.prod(stream.dims)

@@ -20,6 +20,12 @@
  *  - Calls are synchronous with respect to the host: when a call returns, its
  *    device work on the handle's stream has finished and the inputs may be
  *    reused. A handle must not be used from two threads at once.
+ *  - Streams: a `stream` argument is a hipStream_t of the HIP runtime this
+ *    library links (libamdhip64.so.7), or NULL for that runtime's null stream.
+ *    A process may hold a second HIP runtime (for example one bundled with a
+ *    Python framework); its stream handles are not valid here and its queued
+ *    work is not ordered with this library's: the caller must finish the work
+ *    that produces an input (or last used an output buffer) before the call.
  *  - st_update is transactional: on any error the decomposition is unchanged.
  */
 #ifndef STUCKER_H
@@ -66,8 +72,8 @@ typedef struct st_config {
                                   Alg. 4 in which ||E_k|| is re-evaluated with FP64
                                   products; 0 = default (1e-2 FP32, 1e-1 bf16x3) */
   int64_t max_rank_d;          /* cap on the streaming rank r_d; 0 = no cap */
-  void *stream;                /* hipStream_t to run on; NULL = the default (null)
-                                  stream, which orders with all other work */
+  void *stream;                /* hipStream_t (of this library's HIP runtime) to
+                                  run on; NULL = that runtime's null stream */
   int32_t profile;             /* nonzero: time every kernel group with HIP events */
 } st_config;
 
@@ -183,7 +189,7 @@ int st_reconstruct_slice(const st_handle *h, int64_t t, float *out);
  * dims[mode] replaced by rows. If norms (host, 2 doubles) is not NULL it
  * receives ||X - (X x_mode A) x_mode A^T||_F^2 and ||X||_F^2 in FP64, the
  * residual and norm of Alg. 4 (rows <= 256 then). precision: enum
- * st_precision. stream: hipStream_t or NULL for the default stream; the call
+ * st_precision. stream: hipStream_t or NULL for the null stream; the call
  * returns after the work has finished. Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
 int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
            int64_t rows, float *out, double *norms, int32_t precision, void *stream);
@@ -200,6 +206,48 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
 int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
             int64_t rows, double *g, int32_t gram_precision, void *stream);
 
+/* ---- Differentiation of the Tucker model (stateless) ----
+ *
+ * Reconstruct: X^ = G x_1 U_1 ... x_d U_d; Project: G = X x_1 U_1^T ... x_d U_d^T
+ * (the multi-TTM form of Sec. 2.1, whose mode-k unfolding is U_k G_(k) K_k^T
+ * with K_k the Kronecker product of the other factors). Shapes: dims
+ * n_1..n_d, ranks r_1..r_d (1 <= r_k <= n_k, nmodes = d <= ST_MAX_MODES).
+ * G has shape r_1 x ... x r_d, X and X^ have shape n_1 x ... x n_d, all
+ * column-major float32 device arrays. factors is a host array of d device
+ * pointers; U_k is column-major n_k x r_k float32. precision (enum
+ * st_precision) selects the product arithmetic of every mode-k TTM; sums of
+ * the factor gradients are FP64. work is a device workspace of at least the
+ * size st_tucker_workspace returns (the caller owns it; it holds factor copies
+ * and the intermediate partial chains and may be reused across calls on one
+ * stream). The work runs on stream (hipStream_t, NULL = null stream) and the
+ * call returns after it has finished.
+ * Errors: ST_EINVAL (shapes, op, null pointers), ST_ESMALL (work too small),
+ * ST_ENOMEM, ST_EHIP. */
+enum st_tucker_op { ST_RECONSTRUCT = 0, ST_PROJECT = 1 };
+
+/* Workspace bytes for st_tucker_fwd / st_tucker_bwd with these shapes. */
+int st_tucker_workspace(int32_t nmodes, const int64_t *dims, const int64_t *ranks,
+                        int32_t precision, int64_t *bytes);
+
+/* Forward: op ST_RECONSTRUCT maps in = G to out = X^; ST_PROJECT maps in = X
+ * to out = G. */
+int st_tucker_fwd(int32_t op, int32_t nmodes, const int64_t *dims, const int64_t *ranks,
+                  const float *in, const float *const *factors, float *out, int32_t precision,
+                  void *work, int64_t work_bytes, void *stream);
+
+/* Vector-Jacobian products at (in, factors) for the upstream gradient gout:
+ *  ST_RECONSTRUCT (in = G, gout shaped like X^): gin = gout x_1 U_1^T ... x_d U_d^T,
+ *    gfactors[k] = (gout x_{j != k} U_j^T)_(k) G_(k)^T;
+ *  ST_PROJECT (in = X, gout shaped like G): gin = gout x_1 U_1 ... x_d U_d,
+ *    gfactors[k] = (X x_{j != k} U_j^T)_(k) gout_(k)^T.
+ * gfactors[k] is a column-major n_k x r_k device array. gin may be NULL, and
+ * gfactors (or any entry of it) may be NULL to skip that output. The partial
+ * chains are recomputed from a shared prefix, not saved from the forward. */
+int st_tucker_bwd(int32_t op, int32_t nmodes, const int64_t *dims, const int64_t *ranks,
+                  const float *in, const float *const *factors, const float *gout, float *gin,
+                  float *const *gfactors, int32_t precision, void *work, int64_t work_bytes,
+                  void *stream);
+
 /* Copy the per-group profile (ST_K_GROUPS entries) into out; reset = 1 also
  * clears the counters. Errors: ST_EINVAL. */
 int st_profile(st_handle *h, st_kernel_profile *out, int32_t count, int32_t reset);
@@ -207,7 +255,8 @@ int st_profile(st_handle *h, st_kernel_profile *out, int32_t count, int32_t rese
 /* Free every resource of the handle (NULL is allowed). */
 void st_destroy(st_handle *h);
 
-/* Message for the last failure on h (or of the last st_create when h is NULL). */
+/* Message for the last failure on h (or, when h is NULL, of the last st_create,
+ * st_tucker_workspace, st_tucker_fwd or st_tucker_bwd on this thread). */
 const char *st_last_error(const st_handle *h);
 
 #ifdef __cplusplus

@@ -5,6 +5,14 @@ plain pointers and sizes through. ``StreamingTucker`` is a convenience wrapper
 that hands torch device tensors (float32, column-major slices) to those calls;
 every arithmetic step runs in the library's kernels. If the library is not
 built this module raises on import: there is no fallback path.
+
+torch here carries its own copy of the HIP runtime with the same soname as the
+system one the library links. Importing torch first makes the dynamic loader
+bind the library to that already-loaded copy, so one runtime serves both; the
+module refuses to load if two copies end up mapped (they would each claim the
+GPU). Every wrapper still finishes torch's queued work first (``_ready``) and
+runs the library on the runtime's null stream (or on a raw stream handle passed
+as an int); library calls return after their device work has finished.
 """
 
 from __future__ import annotations
@@ -32,7 +40,9 @@ STATUS_NAMES = {
 
 EXPORTED = ["st_create", "st_init", "st_update", "st_ranks", "st_core", "st_factor",
             "st_sv", "st_recon_error", "st_stats", "st_reconstruct_slice",
-            "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile", "st_aux_v"]
+            "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile", "st_aux_v",
+            "st_tucker_workspace", "st_tucker_fwd", "st_tucker_bwd"]
+ST_RECONSTRUCT, ST_PROJECT = 0, 1
 
 KERNEL_GROUPS = ["ttm1", "ttm", "gram", "eig", "ttm_ext", "isvd", "svd", "rot_v", "rot_c",
                  "ud"]
@@ -83,7 +93,22 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                       "python paper_2308_16395_amd/build.py")
 
+try:
+    import torch  # noqa: F401  (load torch's HIP runtime before the library)
+except ImportError:  # pragma: no cover - the binding's tensors are torch tensors
+    torch = None
+
+
+def _hip_runtimes():
+    with open("/proc/self/maps") as f:
+        return {line.split()[-1] for line in f if "libamdhip64" in line.split()[-1]}
+
+
 lib = C.CDLL(LIB_PATH)
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are mapped in this process "
+                      f"({sorted(_hip_runtimes())}); import paper_2308_16395_amd (or torch) "
+                      "before anything that loads the system libamdhip64")
 _h = C.c_void_p
 _sig = {
     "st_create": (C.c_int, [C.POINTER(st_config), C.POINTER(_h)]),
@@ -103,6 +128,15 @@ _sig = {
     "st_gram": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_void_p,
                           C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
     "st_profile": (C.c_int, [_h, C.POINTER(st_kernel_profile), C.c_int32, C.c_int32]),
+    "st_tucker_workspace": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.c_int32, C.POINTER(C.c_int64)]),
+    "st_tucker_fwd": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64), C.c_void_p, C.POINTER(C.c_void_p),
+                                C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
+    "st_tucker_bwd": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64), C.c_void_p, C.POINTER(C.c_void_p),
+                                C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_int32,
+                                C.c_void_p, C.c_int64, C.c_void_p]),
     "st_destroy": (None, [_h]),
     "st_last_error": (C.c_char_p, [_h]),
 }
@@ -125,8 +159,28 @@ st_reconstruct_slice = lib.st_reconstruct_slice
 st_ttm = lib.st_ttm
 st_gram = lib.st_gram
 st_profile = lib.st_profile
+st_tucker_workspace = lib.st_tucker_workspace
+st_tucker_fwd = lib.st_tucker_fwd
+st_tucker_bwd = lib.st_tucker_bwd
 st_destroy = lib.st_destroy
 st_last_error = lib.st_last_error
+
+
+def _ready():
+    """Finish torch's queued device work before a library call reads or writes
+    torch-allocated memory."""
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def _stream_arg(stream):
+    """NULL (the library runtime's null stream) or a raw hipStream_t of that runtime."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    raise TypeError("stream must be None or a raw hipStream_t (int) of the library's runtime")
 
 
 class StError(RuntimeError):
@@ -147,11 +201,10 @@ def ttm(x, dims, mode, a, precision="fp32", norms=False, stream=None):
     out = torch.empty(out_elems, dtype=torch.float32, device=x.device)
     cdims = (C.c_int64 * len(dims))(*dims)
     nrm = (C.c_double * 2)() if norms else None
-    if stream is None:
-        stream = torch.cuda.current_stream()
+    _ready()
     rc = st_ttm(C.c_void_p(x.data_ptr()), len(dims), cdims, int(mode), C.c_void_p(a.data_ptr()),
                 rows, C.c_void_p(out.data_ptr()), nrm,
-                PRECISIONS[precision], C.c_void_p(stream.cuda_stream))
+                PRECISIONS[precision], _stream_arg(stream))
     if rc != ST_OK:
         raise StError(rc, "st_ttm failed")
     if norms:
@@ -169,13 +222,12 @@ def gram(x, dims, mode, a=None, precision="fp64", stream=None):
     n = dims[mode]
     g = np.zeros(n * n)
     cdims = (C.c_int64 * len(dims))(*dims)
-    if stream is None:
-        stream = torch.cuda.current_stream()
     rows = 0 if a is None else int(a.shape[0])
+    _ready()
     rc = st_gram(C.c_void_p(x.data_ptr()), len(dims), cdims, int(mode),
                  C.c_void_p(a.data_ptr() if a is not None else 0), rows,
                  g.ctypes.data_as(C.c_void_p), {"fp32": 0, "bf16x3": 1, "fp64": 2}[precision],
-                 C.c_void_p(stream.cuda_stream))
+                 _stream_arg(stream))
     if rc != ST_OK:
         raise StError(rc, "st_gram failed")
     return g.reshape(n, n, order="F")
@@ -207,10 +259,7 @@ class StreamingTucker:
         cfg.guard_rel = float(guard_rel)
         cfg.max_rank_d = int(max_rank_d)
         cfg.profile = 1 if profile else 0
-        if stream is None:
-            stream = torch.cuda.current_stream()
-        cfg.stream = C.c_void_p(stream.cuda_stream)
-        self._stream = stream
+        cfg.stream = _stream_arg(stream)
         h = _h()
         rc = st_create(C.byref(cfg), C.byref(h))
         if rc != ST_OK:
@@ -222,6 +271,10 @@ class StreamingTucker:
     def _check(self, rc):
         if rc != ST_OK:
             raise StError(rc, st_last_error(self._h).decode())
+
+    def _call(self, fn, *args):
+        _ready()
+        self._check(fn(self._h, *args))
 
     def _dev(self, x, count):
         t = self._torch
@@ -242,10 +295,10 @@ class StreamingTucker:
             pass
 
     def init(self, x0, n_init):
-        self._check(st_init(self._h, self._dev(x0, self.slice_elems * n_init), int(n_init)))
+        self._call(st_init, self._dev(x0, self.slice_elems * n_init), int(n_init))
 
     def update(self, y):
-        self._check(st_update(self._h, self._dev(y, self.slice_elems)))
+        self._call(st_update, self._dev(y, self.slice_elems))
 
     @property
     def ranks(self):
@@ -267,7 +320,7 @@ class StreamingTucker:
         need = C.c_int64()
         self._check(st_core(self._h, None, 0, C.byref(need), ST_DEVICE))
         out = t.empty(need.value, dtype=t.float32, device="cuda")
-        self._check(st_core(self._h, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE))
+        self._call(st_core, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE)
         return out
 
     def aux_v(self):
@@ -276,7 +329,7 @@ class StreamingTucker:
         need = C.c_int64()
         self._check(st_aux_v(self._h, None, 0, C.byref(need), ST_DEVICE))
         out = t.empty(need.value, dtype=t.float64, device="cuda")
-        self._check(st_aux_v(self._h, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE))
+        self._call(st_aux_v, C.c_void_p(out.data_ptr()), need.value, None, ST_DEVICE)
         rd = self.ranks[-1]
         return out.reshape(rd, -1).T
 
@@ -286,8 +339,8 @@ class StreamingTucker:
         rows, cols = C.c_int64(), C.c_int64()
         self._check(st_factor(self._h, mode, None, 0, C.byref(rows), C.byref(cols), ST_DEVICE))
         out = t.empty(rows.value * cols.value, dtype=t.float64, device="cuda")
-        self._check(st_factor(self._h, mode, C.c_void_p(out.data_ptr()), out.numel(),
-                              None, None, ST_DEVICE))
+        self._call(st_factor, mode, C.c_void_p(out.data_ptr()), out.numel(), None, None,
+                   ST_DEVICE)
         return out.reshape(cols.value, rows.value).T  # (rows, cols) view
 
     def factors(self):
@@ -326,5 +379,5 @@ class StreamingTucker:
         t = self._torch
         if out is None:
             out = t.empty(self.slice_elems, dtype=t.float32, device="cuda")
-        self._check(st_reconstruct_slice(self._h, int(t_index), self._dev(out, self.slice_elems)))
+        self._call(st_reconstruct_slice, int(t_index), self._dev(out, self.slice_elems))
         return out

@@ -54,7 +54,7 @@ struct DBuf {
   }
 };
 
-thread_local std::string g_create_error;
+thread_local std::string g_create_error;  // st_create and the stateless calls
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -83,6 +83,10 @@ void rank_rule(const double *lam_asc, int64_t n, double eps, int64_t &r, double 
 }
 
 }  // namespace
+
+namespace st {
+void set_stateless_error(const char *msg) { g_create_error = msg ? msg : ""; }
+}  // namespace st
 
 struct st_handle {
   // configuration
@@ -1081,6 +1085,8 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
   if (norms && rows > 256) return ST_EINVAL;
   const int64_t nk = dims[mode];
   hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;  // initialises the runtime
   FiberIn in{};
   in.x = x;
   in.a = lo;
@@ -1142,6 +1148,8 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
   const int64_t nk = dims[mode];
   if (nk > (gram_precision == 2 ? 256 : 512) || rows > nk) return ST_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;  // initialises the runtime
   FiberIn in{};
   in.x = x;
   in.a = lo;

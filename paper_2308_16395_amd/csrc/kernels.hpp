@@ -47,4 +47,7 @@ hipError_t launch_split_rows(const float *w, int64_t rows, int64_t n, int64_t ld
 
 hipError_t launch_f32_to_f64(const float *x, int64_t n, double *y, hipStream_t s);
 
+// Message for st_last_error(NULL) after a failed stateless call.
+void set_stateless_error(const char *msg);
+
 }  // namespace st
