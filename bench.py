@@ -33,6 +33,16 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "blobs128_oracle_trajectory.json"
 WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_init=20,
                 tau=1e-4, seed=1001)
 
+# HBM bytes per launch of the dominant kernel of the FP32 headline run, from the
+# two counter passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, calibrated on a
+# 1 GiB copy) recorded in profiles/stream_update_blobs128x16_fp32_hbm_traffic.md.
+# Only reported while the kernel and workload are those the counters were taken on.
+MEASURED_TRAFFIC = {("fp32", "rot_v"): 1.445e9}
+
+# Differentiation workload: a 96^3 x 8 variables x 16-slice window, ranks
+# (24, 24, 24, 6, 8).
+GRAD_DIMS, GRAD_RANKS = (96, 96, 96, 8, 16), (24, 24, 24, 6, 8)
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -59,8 +69,77 @@ def roofline(prof, precision):
                      frac=round(achieved / PEAK_HBM_GBS, 4))
     entry.update(kernel=group, launches=p["launches"], avg_ms=round(p["ms"] / p["launches"], 5),
                  flops_per_launch=p["flops"] / p["launches"],
-                 bytes_per_launch=p["bytes"] / p["launches"], traffic=None)
+                 bytes_per_launch=p["bytes"] / p["launches"],
+                 traffic=MEASURED_TRAFFIC.get((precision, group)))
     return group, entry
+
+
+def ttm_roofline(prof, precision):
+    """Roofline of the mode-1 TTM with its fused residual (the largest contraction)."""
+    p = prof["ttm1"]
+    if not p["launches"] or p["ms"] <= 0:
+        return None
+    sec = p["ms"] / 1e3
+    peak_f = PEAK_TFLOPS[precision]
+    ridge = peak_f * 1e12 / (PEAK_HBM_GBS * 1e9)
+    ai = p["flops"] / p["bytes"]
+    t_floor = max(p["flops"] / (peak_f * 1e12), p["bytes"] / (PEAK_HBM_GBS * 1e9))
+    return dict(kernel="ttm1", bound="mfma" if ai >= ridge else "hbm",
+                achieved_tflops=round(p["flops"] / sec / 1e12, 3),
+                achieved_gbs=round(p["bytes"] / sec / 1e9, 1),
+                avg_ms=round(p["ms"] / p["launches"], 5), frac=round(t_floor / sec, 4))
+
+
+def ttm_chain_flops(shape, modes_to):
+    """Flops of the mode-by-mode TTM chain changing shape[k] to modes_to[k]."""
+    shape = list(shape)
+    total = 0.0
+    for k, m in enumerate(modes_to):
+        total += 2.0 * math.prod(shape) * m
+        shape[k] = m
+    return total
+
+
+def grad_bench(reps=5):
+    """Reconstruct / Project forward and VJPs at GRAD_DIMS, FP32 products."""
+    import numpy as np
+    import torch
+
+    import paper_2308_16395_amd.autodiff as ad
+
+    rng = np.random.default_rng(7)
+    facs = [ad.colmajor(torch.from_numpy(np.linalg.qr(rng.standard_normal((n, r)))[0]
+                                         .astype(np.float32)).cuda())
+            for n, r in zip(GRAD_DIMS, GRAD_RANKS)]
+    core = torch.randn(math.prod(GRAD_RANKS), device="cuda")
+    xhat = ad.tucker_reconstruct(core, facs)
+    x = xhat + 0.01 * torch.randn_like(xhat)
+    upstream = 2.0 * (xhat - x)
+    gbar = torch.randn_like(core)
+    ops = {
+        "reconstruct": lambda: ad.tucker_reconstruct(core, facs),
+        "reconstruct_vjp": lambda: ad.tucker_reconstruct_vjp(core, facs, upstream),
+        "project": lambda: ad.tucker_project(x, facs),
+        "project_vjp": lambda: ad.tucker_project_vjp(x, facs, gbar),
+    }
+    f_rec = ttm_chain_flops(GRAD_RANKS, GRAD_DIMS)
+    f_proj = ttm_chain_flops(GRAD_DIMS, GRAD_RANKS)
+    out = {}
+    for name, fn in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        flops = f_rec if name == "reconstruct" else f_proj if name == "project" else None
+        out[name] = dict(ms=round(ms, 3))
+        if flops:
+            out[name]["tflops"] = round(flops / ms / 1e9, 2)
+    return dict(workload="Reconstruct/Project and VJPs, 96x96x96 x 8 variables x 16-slice "
+                         "window, ranks (24, 24, 24, 6, 8), FP32 MFMA, wall time per call",
+                **out)
 
 
 def cpu_baseline(host_slices, n_init, tau, n_updates):
@@ -95,10 +174,12 @@ def main():
     ap.add_argument("--steps", type=int, default=375)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32")
-    ap.add_argument("--cpu-updates", type=int, default=6)
+    ap.add_argument("--cpu-updates", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the Reconstruct/Project forward and VJP timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size "
                          "kernel against which HBM byte counters are calibrated)")
@@ -206,6 +287,7 @@ def main():
             "eps": w["tau"], "precision": args.precision, "seed": w["seed"],
         },
         "roofline": roof,
+        "ttm_roofline": ttm_roofline(prof, args.precision),
         "kernels": {g: dict(launches=p["launches"], ms=round(p["ms"], 3),
                             tflops=round(p["flops"] / p["ms"] / 1e9, 3) if p["ms"] else None,
                             gbs=round(p["bytes"] / p["ms"] / 1e6, 1) if p["ms"] else None)
@@ -228,6 +310,12 @@ def main():
                 for t in range(n_init + k)]
         log(f"timing the FP64 oracle on {k} updates")
         result["cpu_baseline"] = cpu_baseline(host, n_init, w["tau"], k)
+        del host
+    if not args.no_grad:
+        del data
+        torch.cuda.empty_cache()
+        log("timing Reconstruct/Project forward and VJPs")
+        result["differentiation"] = grad_bench()
     print(json.dumps(result), flush=True)
 
 

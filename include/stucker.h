@@ -75,7 +75,20 @@ typedef struct st_config {
   void *stream;                /* hipStream_t (of this library's HIP runtime) to
                                   run on; NULL = that runtime's null stream */
   int32_t profile;             /* nonzero: time every kernel group with HIP events */
+  int32_t core_update;         /* enum st_core_update */
 } st_config;
+
+/* How the core and the auxiliary V are carried between slices.
+ * ST_CORE_LITERAL: the last step of Alg. 5 as stated: V and the core C are
+ *   both rotated on every slice (C~_(d) = U''^T [C_(d); d^T]); the core keeps
+ *   the part of an ignored slice's residual that Alg. 3 drops from V.
+ * ST_CORE_FACTORED: the core is C = V x_d S (the Ensure clause of Alg. 5) and V
+ *   is kept as the product V0 M of a matrix V0 whose columns are only ever
+ *   appended (one per growing slice) and a small orthogonal r_d x r_d matrix M
+ *   (the factored ISVD the paper names as future work, Sec. 3.2 and Sec. 6).
+ *   Per slice this replaces the two rotations of R x r_d matrices by r_d x r_d
+ *   work; rank decisions are the same as with ST_CORE_LITERAL. */
+enum st_core_update { ST_CORE_LITERAL = 0, ST_CORE_FACTORED = 1 };
 
 /* Kernel groups timed when st_config.profile is set. */
 enum st_kernel_group {

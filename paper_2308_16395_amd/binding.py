@@ -30,6 +30,7 @@ ST_ENONFINITE, ST_EDEGENERATE, ST_ESMALL, ST_ECAPACITY, ST_ESOLVER = -5, -6, -7,
 ST_FP32, ST_BF16X3, ST_FP64 = 0, 1, 2
 PRECISIONS = {"fp32": ST_FP32, "bf16x3": ST_BF16X3, "fp64": ST_FP64}
 ST_HOST, ST_DEVICE = 0, 1
+CORE_UPDATES = {"literal": 0, "factored": 1}
 
 STATUS_NAMES = {
     ST_OK: "ST_OK", ST_EINVAL: "ST_EINVAL", ST_ENOMEM: "ST_ENOMEM", ST_EHIP: "ST_EHIP",
@@ -59,6 +60,7 @@ class st_config(C.Structure):
         ("max_rank_d", C.c_int64),
         ("stream", C.c_void_p),
         ("profile", C.c_int32),
+        ("core_update", C.c_int32),
     ]
 
 
@@ -242,7 +244,7 @@ class StreamingTucker:
     """
 
     def __init__(self, dims, tau, precision="fp32", orth_tol=0.0, guard_rel=0.0,
-                 max_rank_d=0, stream=None, profile=False):
+                 max_rank_d=0, stream=None, profile=False, core_update="literal"):
         import torch
 
         self._torch = torch
@@ -259,6 +261,8 @@ class StreamingTucker:
         cfg.guard_rel = float(guard_rel)
         cfg.max_rank_d = int(max_rank_d)
         cfg.profile = 1 if profile else 0
+        cfg.core_update = CORE_UPDATES[core_update]
+        self.core_update = core_update
         cfg.stream = _stream_arg(stream)
         h = _h()
         rc = st_create(C.byref(cfg), C.byref(h))

@@ -106,6 +106,7 @@ struct st_handle {
 
   // decomposition
   bool inited = false;
+  bool factored = false;  // ST_CORE_FACTORED: V = V0 M, C = V x_d S
   int64_t r[ST_MAX_MODES] = {};
   int64_t rd = 0, nd = 0;
   double xnorm2 = 0.0, disc = 0.0;
@@ -127,6 +128,12 @@ struct st_handle {
   DBuf<double> V[2];  // auxiliary matrix (FP64 in every form: it decides the ISVD test)
   DBuf<float> C[2];   // core, mode-d unfolding transposed
   int cur = 0;
+  // factored form: V[v0cur] holds V0 (rows at the current ranks, ld = R);
+  // Mf[cur] holds M (r_d x r_d, ld r_d)
+  int v0cur = 0;
+  DBuf<double> Mf[2];
+  DBuf<double> tvec, wvec, e1buf, tmp64;
+  DBuf<float> tmp32;
 
   // work buffers
   DBuf<double> D[2];   // partial cores D*_k of the update (FP64)
@@ -358,6 +365,10 @@ struct st_handle {
 
   int do_init(const float *x0, int64_t n_init);
   int do_update(const float *y);
+  int stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
+                      double eps, st_slice_stats &stt, int &grow, double &q2, int64_t &c,
+                      int &v0next);
+  hipError_t factored_product(const double *S_or_null, double *out64);
   int do_reconstruct_slice(int64_t t, float *out);
   void destroy();
 };
@@ -468,13 +479,18 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
       if (e == hipSuccess)
         e = hipMemcpyAsync(S[cur].p, S_host.data(), rk * sizeof(double), hipMemcpyHostToDevice,
                            stream);
-      if (e == hipSuccess) e = V[cur].ensure((size_t)(R * rk));
-      if (e == hipSuccess) e = C[cur].ensure((size_t)(R * rk));
+      // factored form: room for later appended columns of V0; M = I
+      if (e == hipSuccess)
+        e = V[cur].ensure(factored ? (size_t)R * (rk + 16) : (size_t)(R * rk));
+      if (e == hipSuccess && !factored) e = C[cur].ensure((size_t)(R * rk));
+      if (e == hipSuccess && factored) e = Mf[cur].ensure((size_t)(rk * rk));
+      if (e == hipSuccess && factored) e = launch_identity(Mf[cur].p, (int)rk, stream);
+      v0cur = cur;
       // V = A^T U_d S^-1 and C_(d)^T = A^T U_d, A = C*_{d-1,(d)} (FP64 accumulation)
       if (e == hipSuccess && !din64) e = hipErrorInvalidValue;  // d >= 2: A is a partial core
       if (e == hipSuccess)
         e = launch_init_vc(static_cast<const double *>(Din), R, n_init, Ud[cur].p, ldu, (int)rk,
-                           S[cur].p, V[cur].p, C[cur].p, stream);
+                           S[cur].p, V[cur].p, factored ? nullptr : C[cur].p, stream);
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (e != hipSuccess) {
         rc = hipfail(e, "init core");
@@ -606,6 +622,31 @@ int st_handle::do_update(const float *y) {
   }
   if (!din64) return fail(ST_EINVAL, "slice has no slice modes");
   const double *dvec = static_cast<const double *>(Din);
+  if (factored) {
+    int growf = 0, v0next = v0cur;
+    double q2f = 0.0;
+    int64_t cf = 0;
+    rc = stream_factored(map, dvec, Rold, Rnew, eps, stt, growf, q2f, cf, v0next);
+    if (rc != ST_OK) return rc;
+    // ---- commit ----
+    S_host.assign(hpin, hpin + cf);
+    for (int k = 0; k < m; ++k) r[k] = rn[k];
+    rd = cf;
+    nd += 1;
+    cur ^= 1;
+    v0cur = v0next;
+    xnorm2 += ynorm2;
+    if (!growf) delta2 += q2f;
+    disc += delta2;
+    stt.ynorm = std::sqrt(ynorm2);
+    stt.eps = eps;
+    stt.delta2 = delta2;
+    stt.ms_modes = ms_modes;
+    stt.ms_total = ms_since(t0);
+    stt.ms_isvd = stt.ms_total - ms_modes;
+    stats = stt;
+    return ST_OK;
+  }
   const int rdi = (int)rd;
   const int nb = isvd_blocks(Rnew);
   e = colpart.ensure((size_t)nb * rdi);
@@ -758,6 +799,173 @@ int st_handle::do_update(const float *y) {
   return ST_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Alg. 3 in the factored form V = V0 M. V0 is brought to the row layout of the
+// new slice-mode ranks (only when one of them grew), then
+//   t1 = V0^T d, p1 = M^T t1;  e1 = d - V0 (M p1), t2 = V0^T e1, p2 = M^T t2,
+// so p = p1 + p2 = V^T d to two Gram-Schmidt passes and q^2 = ||e1||^2 - ||p2||^2.
+// A growing slice appends v = (e1 - V0 M p2) / q as a new column of V0; in every
+// case M~ = blockdiag(M, 1) V'' and U_d, S are updated as in the literal form.
+// On success hpin[0 .. c) holds the new singular values.
+// ---------------------------------------------------------------------------
+int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
+                               double eps, st_slice_stats &stt, int &grow, double &q2,
+                               int64_t &c, int &v0next) {
+  const int rdi = (int)rd;
+  const int nxt = cur ^ 1;
+  hipError_t e = hipSuccess;
+  int w0 = v0cur;
+  const size_t need = (size_t)Rnew * (size_t)(rd + 1);
+  if (!map.identity || V[v0cur].cap < need) {
+    // relayout (or grow the column capacity) into the other buffer; the
+    // committed V0 stays untouched until the commit
+    w0 = v0cur ^ 1;
+    e = V[w0].ensure(std::max(need, (size_t)Rnew * (size_t)(rd + 16)));
+    if (e == hipSuccess) {
+      if (!map.identity)
+        e = launch_remap_rows(V[v0cur].p, Rold, map, Rnew, rdi, V[w0].p, stream);
+      else
+        e = hipMemcpyAsync(V[w0].p, V[v0cur].p, (size_t)Rold * rd * sizeof(double),
+                           hipMemcpyDeviceToDevice, stream);
+    }
+    if (e != hipSuccess) return hipfail(e, "V0 relayout");
+  }
+  double *V0 = V[w0].p;
+  const double *M = Mf[cur].p;
+  const int nb = isvd_blocks(Rnew);
+  e = colpart.ensure((size_t)nb * rdi);
+  if (e == hipSuccess) e = q2part.ensure(nb);
+  if (e == hipSuccess) e = p1.ensure(rdi);
+  if (e == hipSuccess) e = p2.ensure(rdi);
+  if (e == hipSuccess) e = p.ensure(rdi);
+  if (e == hipSuccess) e = tvec.ensure(2 * (size_t)rdi);
+  if (e == hipSuccess) e = wvec.ensure(2 * (size_t)rdi);
+  if (e == hipSuccess) e = e1buf.ensure(Rnew);
+  if (e != hipSuccess) return hipfail(e, "isvd buffers");
+  double *t1 = tvec.p, *t2 = tvec.p + rdi, *w1 = wvec.p, *w2 = wvec.p + rdi;
+  RowMap ident{};
+  ident.nm = m;
+  ident.identity = 1;
+  IsvdArgs ia{};
+  ia.V = V0;
+  ia.ldv = Rnew;
+  ia.r = rdi;
+  ia.R = Rnew;
+  ia.map = ident;
+  ia.d = dvec;
+  ia.p1 = w1;
+  ia.colpart = colpart.p;
+  ia.q2part = q2part.p;
+  ia.e1out = e1buf.p;
+  tic();
+  e = launch_isvd_pass(1, ia, nb, stream);
+  if (e == hipSuccess)
+    e = launch_colsum(colpart.p, nb, rdi, t1, nullptr, nullptr, nullptr, nullptr, stream);
+  if (e == hipSuccess) e = launch_small_gemv(M, rdi, t1, 1, p1.p, nullptr, nullptr, stream);
+  if (e == hipSuccess) e = launch_small_gemv(M, rdi, p1.p, 0, w1, nullptr, nullptr, stream);
+  if (e == hipSuccess) e = launch_isvd_pass(2, ia, nb, stream);
+  if (e == hipSuccess)
+    e = launch_colsum(colpart.p, nb, rdi, t2, nullptr, nullptr, q2part.p, sums.p, stream);
+  if (e == hipSuccess) e = launch_small_gemv(M, rdi, t2, 1, p2.p, p1.p, p.p, stream);
+  // V0 read twice, d read twice, e1 written once (FP64)
+  toc(ST_K_ISVD, 6.0 * Rnew * rdi, 2.0 * 8.0 * Rnew * rdi + 3.0 * 8.0 * Rnew);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hpin, sums.p, sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hpin + 1, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hpin + 1 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
+                       stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "isvd projections");
+  settle();
+  const double e1sq = hpin[0];
+  double pmax = 0.0, p2max = 0.0, p2sq = 0.0;
+  for (int j = 0; j < rdi; ++j) {
+    pmax = std::max(pmax, std::fabs(hpin[1 + j]));
+    const double v2 = hpin[1 + rdi + j];
+    p2max = std::max(p2max, std::fabs(v2));
+    p2sq += v2 * v2;
+  }
+  q2 = std::max(e1sq - p2sq, 0.0);
+  const double q = std::sqrt(q2);
+  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+  const double tol = 8.0 * 0x1p-53 * std::max({S_host.empty() ? 0.0 : S_host[0], pmax, q});
+  grow = (q > eps && q > tol) ? 1 : 0;
+  c = rd + grow;
+  stt.q = q;
+  stt.isvd_ignored = grow ? 0 : 1;
+  stt.orth_check = e1sq > 0.0 ? p2max / std::sqrt(e1sq) : 0.0;
+  stt.qr_fired = (grow && stt.orth_check > orth_tol) ? 1 : 0;
+  if (max_rank_d > 0 && c > max_rank_d)
+    return fail(ST_ECAPACITY, "streaming rank %lld exceeds the cap", (long long)c);
+
+  const int64_t nn = rd + 1;
+  e = ensure_secular(nn);
+  if (e == hipSuccess) e = U2.ensure((size_t)nn * c);
+  if (e == hipSuccess) e = V2.ensure((size_t)nn * c);
+  if (e == hipSuccess) e = S[nxt].ensure(c);
+  if (e == hipSuccess) e = Mf[nxt].ensure((size_t)(c * c));
+  int64_t ldn = ud_ld[nxt];
+  if (e == hipSuccess && (ldn < nd + 1 || Ud[nxt].cap < (size_t)ldn * c)) {
+    ldn = std::max<int64_t>(ud_ld[cur], round_up(nd + 1, 64));
+    e = Ud[nxt].ensure((size_t)ldn * c);
+  }
+  if (e != hipSuccess) return hipfail(e, "streaming buffers");
+  ud_ld[nxt] = ldn;
+  tic();
+  e = launch_secular_svd(secdata(rdi), S[cur].p, p.p, q, grow, tol, (int)c, U2.p, V2.p, S[nxt].p,
+                         stream);
+  toc(ST_K_SVD, 60.0 * (double)nn * nn, 8.0 * 4.0 * nn * c);
+  if (e != hipSuccess) return hipfail(e, "small SVD");
+  tic();
+  if (grow) {
+    // v = (e1 - V0 M p2) / q into column r_d of V0
+    e = launch_small_gemv(M, rdi, p2.p, 0, w2, nullptr, nullptr, stream);
+    if (e == hipSuccess)
+      e = launch_vcol(V0, Rnew, rdi, w2, e1buf.p, 1.0 / q, V0 + Rnew * rd, nullptr, stream);
+  }
+  if (e == hipSuccess) e = launch_m_update(M, rdi, V2.p, (int)c, grow, Mf[nxt].p, stream);
+  // the appended column: read V0 and e1, write one column; M~: c^2 r flops
+  toc(ST_K_ROT_V, (grow ? 2.0 * Rnew * rd : 0.0) + 2.0 * (double)c * c * rd,
+      grow ? 8.0 * ((double)Rnew * rd + 2.0 * Rnew) : 8.0 * (double)c * c);
+  if (e != hipSuccess) return hipfail(e, "V0 / M update");
+  tic();
+  e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
+  toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + 1.0) * c));
+  if (e != hipSuccess) return hipfail(e, "streaming factor update");
+  e = hipMemcpyAsync(hpin, S[nxt].p, c * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "streaming update");
+  settle();
+  for (int64_t i = 0; i < c; ++i)
+    if (!std::isfinite(hpin[i]) || hpin[i] <= 0.0)
+      return fail(ST_ESOLVER, "small SVD produced a non-positive singular value");
+  v0next = w0;
+  return ST_OK;
+}
+
+// V0 M diag(S) (S not null: the core C_(d)^T) or V0 M (V) into out64 (R x r_d).
+hipError_t st_handle::factored_product(const double *S_or_null, double *out64) {
+  const int64_t R = rprod(r, m);
+  const int rdi = (int)rd;
+  hipError_t e = wvec.ensure((size_t)rdi * rdi + 2 * (size_t)rdi);
+  if (e != hipSuccess) return e;
+  double *W = wvec.p;
+  e = launch_mt_rows(Mf[cur].p, rdi, S_or_null, W, rdi, stream);
+  if (e != hipSuccess) return e;
+  FiberIn in{};
+  in.x = V[v0cur].p;
+  in.x64 = 1;
+  in.a = R;
+  in.n = rd;
+  in.F = R;
+  in.mapped = 1;
+  in.map.nm = m;
+  in.map.identity = 1;
+  return launch_rot64(in, W, 1, rdi, 0, rdi, FiberOut{out64, 1, R, rd}, 0, nullptr, stream);
+}
+
 // Slice t of C x_1 U_1 ... x_d U_d.
 int st_handle::do_reconstruct_slice(int64_t t, float *out) {
   if (!inited) return fail(ST_ESTATE, "not initialised");
@@ -767,19 +975,31 @@ int st_handle::do_reconstruct_slice(int64_t t, float *out) {
   if (e == hipSuccess) e = RB[0].ensure(NY);
   if (e == hipSuccess) e = RB[1].ensure(NY);
   if (e != hipSuccess) return hipfail(e, "reconstruct buffers");
-  e = launch_ud_row(Ud[cur].p, ud_ld[cur], t, (int)rd, wrow.p, stream);
-  FiberIn in{};
-  in.x = C[cur].p;
-  in.a = R;
-  in.n = rd;
-  in.F = R;
-  FiberW w{};
-  w.w = wrow.p;
-  w.ldw = rd;
-  float *cur_buf = (m == 0) ? out : RB[0].p;
-  if (e == hipSuccess)
-    e = launch_fiber_project(in, w, 0, 1, FiberOut{cur_buf, 0, R, 1}, nullptr, Prec::FP32,
-                             stream);
+  float *cur_buf = RB[0].p;
+  if (factored) {
+    // C x_d U_d(t,:) = V0 (M (S o U_d(t,:))), formed in FP64 and rounded once
+    e = wvec.ensure(2 * (size_t)rd);
+    if (e == hipSuccess)
+      e = launch_ud_row64(Ud[cur].p, ud_ld[cur], t, (int)rd, S[cur].p, wvec.p, stream);
+    if (e == hipSuccess)
+      e = launch_small_gemv(Mf[cur].p, (int)rd, wvec.p, 0, wvec.p + rd, nullptr, nullptr, stream);
+    if (e == hipSuccess)
+      e = launch_vcol(V[v0cur].p, R, (int)rd, wvec.p + rd, nullptr, -1.0, nullptr, cur_buf,
+                      stream);
+  } else {
+    e = launch_ud_row(Ud[cur].p, ud_ld[cur], t, (int)rd, wrow.p, stream);
+    FiberIn in{};
+    in.x = C[cur].p;
+    in.a = R;
+    in.n = rd;
+    in.F = R;
+    FiberW w{};
+    w.w = wrow.p;
+    w.ldw = rd;
+    if (e == hipSuccess)
+      e = launch_fiber_project(in, w, 0, 1, FiberOut{cur_buf, 0, R, 1}, nullptr, Prec::FP32,
+                               stream);
+  }
   int sel = 1;
   int64_t shape[ST_MAX_MODES];
   for (int k = 0; k < m; ++k) shape[k] = r[k];
@@ -821,11 +1041,17 @@ void st_handle::destroy() {
     Ud[i].release();
     S[i].release();
     V[i].release();
+    Mf[i].release();
     C[i].release();
     D[i].release();
     RB[i].release();
   }
   wrow.release();
+  tvec.release();
+  wvec.release();
+  e1buf.release();
+  tmp64.release();
+  tmp32.release();
   part.release();
   sums.release();
   gram_part.release();
@@ -883,7 +1109,8 @@ int st_create(const st_config *cfg, st_handle **out) {
   *out = nullptr;
   if (cfg->nmodes < 1 || cfg->nmodes > ST_MAX_MODES || !(cfg->tau > 0.0) ||
       !std::isfinite(cfg->tau) || cfg->precision < ST_FP32 || cfg->precision > ST_FP64 ||
-      cfg->max_rank_d < 0) {
+      cfg->max_rank_d < 0 ||
+      (cfg->core_update != ST_CORE_LITERAL && cfg->core_update != ST_CORE_FACTORED)) {
     g_create_error = "invalid configuration";
     return ST_EINVAL;
   }
@@ -916,6 +1143,7 @@ int st_create(const st_config *cfg, st_handle **out) {
                      : (h->prec == Prec::BF16X3 ? 0.1 : (h->prec == Prec::FP32 ? 1e-2 : 0.0));
   h->max_rank_d = cfg->max_rank_d;
   h->profile = cfg->profile != 0;
+  h->factored = cfg->core_update == ST_CORE_FACTORED;
   hipError_t e = hipGetDevice(&h->device);
   // the caller's stream, or the null stream (never a private non-blocking one:
   // inputs produced on the default stream must be complete before we read them)
@@ -987,10 +1215,20 @@ int st_core(const st_handle *hc, float *out, int64_t cap, int64_t *need, int whe
   if (!out) return ST_OK;
   if (cap < cnt) return h->fail(ST_ESMALL, "core buffer too small");
   (void)hipSetDevice(h->device);
-  hipError_t e = hipMemcpyAsync(out, h->C[h->cur].p, cnt * sizeof(float),
-                                where == ST_DEVICE ? hipMemcpyDeviceToDevice
-                                                   : hipMemcpyDeviceToHost,
-                                h->stream);
+  const float *src = h->C[h->cur].p;
+  hipError_t e = hipSuccess;
+  if (h->factored) {
+    // C_(d)^T = V0 M diag(S), formed in FP64 and rounded once
+    e = h->tmp64.ensure(cnt);
+    if (e == hipSuccess) e = h->tmp32.ensure(cnt);
+    if (e == hipSuccess) e = h->factored_product(h->S[h->cur].p, h->tmp64.p);
+    if (e == hipSuccess) e = launch_f64_to_f32(h->tmp64.p, cnt, h->tmp32.p, h->stream);
+    src = h->tmp32.p;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, src, cnt * sizeof(float),
+                       where == ST_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->hipfail(e, "core copy");
   return ST_OK;
@@ -1005,10 +1243,17 @@ int st_aux_v(const st_handle *hc, double *out, int64_t cap, int64_t *need, int w
   if (!out) return ST_OK;
   if (cap < cnt) return h->fail(ST_ESMALL, "buffer too small");
   (void)hipSetDevice(h->device);
-  hipError_t e = hipMemcpyAsync(out, h->V[h->cur].p, cnt * sizeof(double),
-                                where == ST_DEVICE ? hipMemcpyDeviceToDevice
-                                                   : hipMemcpyDeviceToHost,
-                                h->stream);
+  const double *src = h->V[h->cur].p;
+  hipError_t e = hipSuccess;
+  if (h->factored) {  // V = V0 M
+    e = h->tmp64.ensure(cnt);
+    if (e == hipSuccess) e = h->factored_product(nullptr, h->tmp64.p);
+    src = h->tmp64.p;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, src, cnt * sizeof(double),
+                       where == ST_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->hipfail(e, "V copy");
   return ST_OK;

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
           double dot = 0.0;
           for (int q = 0; q < SUB; ++q) dot += rowred[q * TR + tid];
           e1 = a.d[row] - dot;
+          if (a.e1out) a.e1out[row] = e1;
         }
         ev[tid] = e1;
         q2 += e1 * e1;
@@ -350,7 +351,7 @@ __global__ void init_vc_kernel(const double *A, int64_t R, int64_t nd, const dou
   for (int m = 0; m < rd; ++m) {
     double acc = 0.0;
     for (int64_t j = 0; j < nd; ++j) acc += A[row + R * j] * Ud[j + ldu * m];
-    Cc[row + R * m] = (float)acc;
+    if (Cc) Cc[row + R * m] = (float)acc;
     V[row + R * m] = acc / S[m];
   }
 }
@@ -527,6 +528,145 @@ __global__ void f32_to_f64_kernel(const float *x, int64_t n, double *y) {
 hipError_t launch_f32_to_f64(const float *x, int64_t n, double *y, hipStream_t s) {
   hipLaunchKernelGGL(f32_to_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
                      y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Factored streaming mode: V = V0 M with V0 (R x r) only ever appended to and
+// the small orthogonal M (r x r) rotated (Sec. 3.2's auxiliary V kept as a
+// product; the core is C = V x_d S).
+// ---------------------------------------------------------------------------
+__global__ void small_gemv_kernel(const double *M, int n, const double *x, int trans, double *y,
+                                  const double *add, double *y2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  if (trans)
+    for (int l = 0; l < n; ++l) acc += M[l + (size_t)n * i] * x[l];
+  else
+    for (int l = 0; l < n; ++l) acc += M[i + (size_t)n * l] * x[l];
+  y[i] = acc;
+  if (y2) y2[i] = acc + add[i];
+}
+
+hipError_t launch_small_gemv(const double *M, int n, const double *x, int trans, double *y,
+                             const double *add, double *y2, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(small_gemv_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, M, n, x,
+                     trans, y, add, y2);
+  return hipGetLastError();
+}
+
+__global__ void vcol_kernel(const double *V0, int64_t R, int r, const double *w,
+                            const double *base, double scale, double *out64, float *out32) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= R) return;
+  double acc = 0.0;
+  for (int l = 0; l < r; ++l) acc += V0[row + R * l] * w[l];
+  const double v = scale * ((base ? base[row] : 0.0) - acc);
+  if (out64) out64[row] = v;
+  if (out32) out32[row] = (float)v;
+}
+
+hipError_t launch_vcol(const double *V0, int64_t R, int r, const double *w, const double *base,
+                       double scale, double *out64, float *out32, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vcol_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, V0, R, r,
+                     w, base, scale, out64, out32);
+  return hipGetLastError();
+}
+
+__global__ void m_update_kernel(const double *M, int r, const double *V2, int c, int grow,
+                                double *Mn) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  const int i = idx % c, j = idx / c;
+  const double *v2c = V2 + (size_t)(r + 1) * j;
+  double acc;
+  if (i < r) {
+    acc = 0.0;
+    for (int l = 0; l < r; ++l) acc += M[i + (size_t)r * l] * v2c[l];
+  } else {  // grow: the appended direction of blockdiag(M, 1)
+    acc = grow ? v2c[r] : 0.0;
+  }
+  Mn[i + (size_t)c * j] = acc;
+}
+
+hipError_t launch_m_update(const double *M, int r, const double *V2, int c, int grow,
+                           double *Mn, hipStream_t s) {
+  const int total = c * c;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(m_update_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M,
+                     r, V2, c, grow, Mn);
+  return hipGetLastError();
+}
+
+__global__ void remap_rows_kernel(const double *src, int64_t ld_src, RowMap map, int64_t Rn,
+                                  int cols, double *dst) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Rn) return;
+  const int64_t o = map_new_to_old(map, row);
+  for (int j = 0; j < cols; ++j) dst[row + Rn * j] = (o >= 0) ? src[o + ld_src * j] : 0.0;
+}
+
+hipError_t launch_remap_rows(const double *src, int64_t ld_src, RowMap map, int64_t Rn,
+                             int cols, double *dst, hipStream_t s) {
+  if (Rn <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(remap_rows_kernel, dim3((unsigned)((Rn + 255) / 256)), dim3(256), 0, s, src,
+                     ld_src, map, Rn, cols, dst);
+  return hipGetLastError();
+}
+
+__global__ void mt_rows_kernel(const double *M, int n, const double *S, double *W, int64_t ldw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int m = idx / n, k = idx % n;
+  W[m * ldw + k] = M[k + (size_t)n * m] * (S ? S[m] : 1.0);
+}
+
+hipError_t launch_mt_rows(const double *M, int n, const double *S, double *W, int64_t ldw,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mt_rows_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, M, n,
+                     S, W, ldw);
+  return hipGetLastError();
+}
+
+__global__ void f64_to_f32_kernel(const double *x, int64_t n, float *y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+hipError_t launch_f64_to_f32(const double *x, int64_t n, float *y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
+                     y);
+  return hipGetLastError();
+}
+
+__global__ void identity_kernel(double *M, int n) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n * n) M[idx] = (idx % n == idx / n) ? 1.0 : 0.0;
+}
+
+hipError_t launch_identity(double *M, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, M,
+                     n);
+  return hipGetLastError();
+}
+
+__global__ void ud_row64_kernel(const double *Ud, int64_t ld, int64_t t, int rd, const double *S,
+                                double *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < rd) out[j] = Ud[t + ld * j] * S[j];
+}
+
+hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, const double *S,
+                           double *out, hipStream_t s) {
+  if (rd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ud_row64_kernel, dim3((unsigned)((rd + 63) / 64)), dim3(64), 0, s, Ud, ld, t,
+                     rd, S, out);
   return hipGetLastError();
 }
 

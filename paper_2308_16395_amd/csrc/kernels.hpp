@@ -16,6 +16,7 @@ struct IsvdArgs {
   const double *p1;    // [r] (pass 2)
   double *colpart;     // [r * nblocks], column-major
   double *q2part;      // [nblocks] (pass 2)
+  double *e1out;       // [R] optional copy of e1 (pass 2)
 };
 
 int isvd_blocks(int64_t R);
@@ -46,6 +47,32 @@ hipError_t launch_split_rows(const float *w, int64_t rows, int64_t n, int64_t ld
                              __bf16 *lo, int64_t ldb, hipStream_t s);
 
 hipError_t launch_f32_to_f64(const float *x, int64_t n, double *y, hipStream_t s);
+
+// ---- factored streaming mode: V = V0 M ----
+// y = M^T x (trans) or M x; M is n x n column-major (ld n). If add is not null
+// also y2 = y + add.
+hipError_t launch_small_gemv(const double *M, int n, const double *x, int trans, double *y,
+                             const double *add, double *y2, hipStream_t s);
+// out[row] = scale * ((base ? base[row] : 0) - sum_l V0[row + R l] w[l]) for
+// row < R, written as FP64 (out64) or FP32 (out32).
+hipError_t launch_vcol(const double *V0, int64_t R, int r, const double *w, const double *base,
+                       double scale, double *out64, float *out32, hipStream_t s);
+// Mn (c x c, ld c) = blockdiag(M, 1)[0:c, 0:rows] V2[0:rows, 0:c] with M r x r
+// (ld r) and V2 (r + 1) x c (ld r + 1); c = r + grow, rows = r + grow.
+hipError_t launch_m_update(const double *M, int r, const double *V2, int c, int grow,
+                           double *Mn, hipStream_t s);
+// dst[row + Rn j] = src[map(row) + ld_src j] (0 for padded rows), j < cols.
+hipError_t launch_remap_rows(const double *src, int64_t ld_src, RowMap map, int64_t Rn,
+                             int cols, double *dst, hipStream_t s);
+// W[m * ldw + k] = M[k + n m] * (S ? S[m] : 1): the row-major rotation matrix of
+// V0 -> V0 M diag(S) for the fibre kernels.
+hipError_t launch_mt_rows(const double *M, int n, const double *S, double *W, int64_t ldw,
+                          hipStream_t s);
+hipError_t launch_f64_to_f32(const double *x, int64_t n, float *y, hipStream_t s);
+hipError_t launch_identity(double *M, int n, hipStream_t s);
+// out[j] = Ud[t + ld j] * S[j], j < rd (row t of U_d S).
+hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, const double *S,
+                           double *out, hipStream_t s);
 
 // Message for st_last_error(NULL) after a failed stateless call.
 void set_stateless_error(const char *msg);

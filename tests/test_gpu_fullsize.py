@@ -26,7 +26,7 @@ def _stream():
     return make_stream(1)
 
 
-def _run(precision):
+def _run(precision, core_update="literal"):
     import torch
 
     import paper_2308_16395_amd as pkg
@@ -37,7 +37,7 @@ def _run(precision):
     dev = torch.device("cuda:0")
     n_init, tau, n = 20, 1e-4, golden["stream"]["n_slices"]
     x0 = torch.cat([s.slice_torch(t, dev, torch.float32) for t in range(n_init)])
-    st = pkg.StreamingTucker(s.dims, tau, precision=precision)
+    st = pkg.StreamingTucker(s.dims, tau, precision=precision, core_update=core_update)
     st.init(x0, n_init)
     assert list(st.ranks) == golden["init_ranks"]
     traj = []
@@ -60,10 +60,13 @@ def _true_error(st, s, n):
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle trajectory not generated")
-def test_fp64_products_reproduce_every_oracle_decision():
+@pytest.mark.parametrize("core_update", ["literal", "factored"])
+def test_fp64_products_reproduce_every_oracle_decision(core_update):
+    """The rank decisions do not depend on how the core is carried, so both
+    forms must follow the same recorded trajectory."""
     import torch
 
-    st, s, golden, traj = _run("fp64")
+    st, s, golden, traj = _run("fp64", core_update)
     ref = [tuple(x["ranks"]) for x in golden["slices"]]
     for i, (a, b) in enumerate(zip(traj, ref)):
         assert a == b, (20 + i, a, b, golden["slices"][i]["q_over_eps"])
@@ -84,9 +87,10 @@ def test_fp64_products_reproduce_every_oracle_decision():
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle trajectory not generated")
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_fast_forms_meet_tau_at_full_size(precision):
-    st, s, golden, traj = _run(precision)
+@pytest.mark.parametrize("precision,core_update",
+                         [("fp32", "literal"), ("bf16x3", "literal"), ("fp32", "factored")])
+def test_fast_forms_meet_tau_at_full_size(precision, core_update):
+    st, s, golden, traj = _run(precision, core_update)
     tau = golden["stream"]["tau"]
     bound, _ = st.recon_error()
     assert bound <= tau
