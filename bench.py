@@ -37,7 +37,7 @@ WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_in
 # two counter passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, calibrated on a
 # 1 GiB copy) recorded in profiles/stream_update_blobs128x16_fp32_hbm_traffic.md.
 # Only reported while the kernel and workload are those the counters were taken on.
-MEASURED_TRAFFIC = {("fp32", "rot_v"): 1.445e9}
+MEASURED_TRAFFIC = {("fp32", "literal", "rot_v"): 1.445e9}
 
 # Differentiation workload: a 96^3 x 8 variables x 16-slice window, ranks
 # (24, 24, 24, 6, 8).
@@ -48,7 +48,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def roofline(prof, precision):
+def roofline(prof, precision, core="literal"):
     """Roofline entry of the group with the most device time."""
     group = max(prof, key=lambda g: prof[g]["ms"])
     p = prof[group]
@@ -70,7 +70,7 @@ def roofline(prof, precision):
     entry.update(kernel=group, launches=p["launches"], avg_ms=round(p["ms"] / p["launches"], 5),
                  flops_per_launch=p["flops"] / p["launches"],
                  bytes_per_launch=p["bytes"] / p["launches"],
-                 traffic=MEASURED_TRAFFIC.get((precision, group)))
+                 traffic=MEASURED_TRAFFIC.get((precision, core, group)))
     return group, entry
 
 
@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--steps", type=int, default=375)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32")
+    ap.add_argument("--core-update", choices=["literal", "factored"], default="literal",
+                    help="literal: Alg. 5 as stated (V and core rotated per slice); factored: "
+                         "V = V0 M and C = V x_d S")
     ap.add_argument("--cpu-updates", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -225,8 +228,9 @@ def main():
         with open(GOLDEN) as f:
             golden = json.load(f)
 
-    def run(precision, want_profile):
-        st = pkg.StreamingTucker(stream.dims, w["tau"], precision=precision, profile=True)
+    def run(precision, core_update):
+        st = pkg.StreamingTucker(stream.dims, w["tau"], precision=precision, profile=True,
+                                 core_update=core_update)
         t0 = time.perf_counter()
         st.init(data[:n_init].reshape(-1), n_init)
         init_s = time.perf_counter() - t0
@@ -262,11 +266,11 @@ def main():
             info["true_rel_error"] = math.sqrt(err2 / nrm2)
             info["eps_met"] = info["true_rel_error"] <= w["tau"]
         st.close()
-        log(f"{precision}: {info}")
+        log(f"{precision} {core_update}: {info}")
         return info, prof
 
-    head, prof = run(args.precision, True)
-    group, roof = roofline(prof, args.precision)
+    head, prof = run(args.precision, args.core_update)
+    group, roof = roofline(prof, args.precision, args.core_update)
     result = {
         "metric": METRIC,
         "value": head["value"],
@@ -284,7 +288,8 @@ def main():
             "workload": "advecting-blobs 128x128x128 x 16 variables, 400 slices, tau 1e-4, "
                         "init 20 slices",
             "slice_dims": list(stream.dims), "n_slices": w["n_slices"], "n_init": n_init,
-            "eps": w["tau"], "precision": args.precision, "seed": w["seed"],
+            "eps": w["tau"], "precision": args.precision, "core_update": args.core_update,
+            "seed": w["seed"],
         },
         "roofline": roof,
         "ttm_roofline": ttm_roofline(prof, args.precision),
@@ -296,14 +301,17 @@ def main():
     result.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
     if not args.no_variants:
         result["variants"] = {}
-        for prec in ("fp64", "bf16x3", "fp32"):
-            if prec == args.precision:
-                continue
-            info, vprof = run(prec, False)
-            vg, vroof = roofline(vprof, prec)
-            info["roofline"] = vroof
-            info["ttm_ms"] = round(vprof["ttm1"]["ms"] + vprof["ttm"]["ms"], 3)
-            result["variants"][prec] = info
+        for core in ("literal", "factored"):
+            for prec in ("fp64", "bf16x3", "fp32"):
+                if (prec, core) == (args.precision, args.core_update):
+                    continue
+                info, vprof = run(prec, core)
+                vg, vroof = roofline(vprof, prec, core)
+                info["roofline"] = vroof
+                info["ttm_ms"] = round(vprof["ttm1"]["ms"] + vprof["ttm"]["ms"], 3)
+                info["kernels_ms"] = {g: round(p["ms"], 2) for g, p in vprof.items()
+                                      if p["launches"]}
+                result["variants"][f"{prec}_{core}"] = info
     if not args.no_cpu_baseline:
         k = args.cpu_updates
         host = [data[t].cpu().numpy().astype(np.float64).reshape(stream.dims, order="F")
