@@ -131,7 +131,7 @@ struct st_handle {
   // factored form: V[v0cur] holds V0 (rows at the current ranks, ld = R);
   // Mf[cur] holds M (r_d x r_d, ld r_d)
   int v0cur = 0;
-  DBuf<double> Mf[2];
+  DBuf<double> Mf[2], Gf[2];  // M and G0 = V0^T V0 (r_d x r_d)
   DBuf<double> tvec, wvec, e1buf, tmp64;
   DBuf<float> tmp32;
 
@@ -485,12 +485,22 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
       if (e == hipSuccess && !factored) e = C[cur].ensure((size_t)(R * rk));
       if (e == hipSuccess && factored) e = Mf[cur].ensure((size_t)(rk * rk));
       if (e == hipSuccess && factored) e = launch_identity(Mf[cur].p, (int)rk, stream);
+      if (e == hipSuccess && factored) e = Gf[cur].ensure((size_t)(rk * rk));
       v0cur = cur;
       // V = A^T U_d S^-1 and C_(d)^T = A^T U_d, A = C*_{d-1,(d)} (FP64 accumulation)
       if (e == hipSuccess && !din64) e = hipErrorInvalidValue;  // d >= 2: A is a partial core
       if (e == hipSuccess)
         e = launch_init_vc(static_cast<const double *>(Din), R, n_init, Ud[cur].p, ldu, (int)rk,
                            S[cur].p, V[cur].p, factored ? nullptr : C[cur].p, stream);
+      if (e == hipSuccess && factored) {
+        // G0 = V0^T V0 (a plain library GEMM, once)
+        const double one = 1.0, zero = 0.0;
+        rocblas_status bs = rocblas_dgemm(rb, rocblas_operation_transpose, rocblas_operation_none,
+                                          (rocblas_int)rk, (rocblas_int)rk, (rocblas_int)R, &one,
+                                          V[cur].p, (rocblas_int)R, V[cur].p, (rocblas_int)R,
+                                          &zero, Gf[cur].p, (rocblas_int)rk);
+        if (bs != rocblas_status_success) e = hipErrorUnknown;
+      }
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (e != hipSuccess) {
         rc = hipfail(e, "init core");
@@ -800,13 +810,15 @@ int st_handle::do_update(const float *y) {
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 3 in the factored form V = V0 M. V0 is brought to the row layout of the
-// new slice-mode ranks (only when one of them grew), then
-//   t1 = V0^T d, p1 = M^T t1;  e1 = d - V0 (M p1), t2 = V0^T e1, p2 = M^T t2,
-// so p = p1 + p2 = V^T d to two Gram-Schmidt passes and q^2 = ||e1||^2 - ||p2||^2.
-// A growing slice appends v = (e1 - V0 M p2) / q as a new column of V0; in every
-// case M~ = blockdiag(M, 1) V'' and U_d, S are updated as in the literal form.
-// On success hpin[0 .. c) holds the new singular values.
+// Alg. 3 in the factored form V = V0 M, with G0 = V0^T V0 kept alongside.
+// V0 is brought to the row layout of the new slice-mode ranks (only when one of
+// them grew). One sweep over V0 gives t1 = V0^T d and ||d||^2; the rest of the
+// two Gram-Schmidt passes is r x r work through G0 (isvd_gram_kernel). When q
+// lands within the rounding bound of that formula of eps, the second pass is
+// redone exactly by a sweep over V0. A growing slice forms e = d - V0 (w1 + w2),
+// V0^T e and ||e||^2 in one fused sweep, appends v = e / q as a new column of V0
+// and extends G0; in every case M~ = blockdiag(M, 1) V'' and U_d, S are updated
+// as in the literal form. On success hpin[0 .. c) holds the new singular values.
 // ---------------------------------------------------------------------------
 int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
                                double eps, st_slice_stats &stt, int &grow, double &q2,
@@ -818,7 +830,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   const size_t need = (size_t)Rnew * (size_t)(rd + 1);
   if (!map.identity || V[v0cur].cap < need) {
     // relayout (or grow the column capacity) into the other buffer; the
-    // committed V0 stays untouched until the commit
+    // committed V0 stays untouched until the commit. Zero rows leave G0 as is.
     w0 = v0cur ^ 1;
     e = V[w0].ensure(std::max(need, (size_t)Rnew * (size_t)(rd + 16)));
     if (e == hipSuccess) {
@@ -832,64 +844,89 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   }
   double *V0 = V[w0].p;
   const double *M = Mf[cur].p;
-  const int nb = isvd_blocks(Rnew);
-  e = colpart.ensure((size_t)nb * rdi);
-  if (e == hipSuccess) e = q2part.ensure(nb);
+  const double *G0 = Gf[cur].p;
+  const int nbg = gemv_t_blocks(Rnew);
+  const int nbp = isvd_blocks(Rnew);
+  e = colpart.ensure((size_t)(rdi + 1) * std::max(nbg, nbp));
+  if (e == hipSuccess) e = q2part.ensure(nbp);
   if (e == hipSuccess) e = p1.ensure(rdi);
   if (e == hipSuccess) e = p2.ensure(rdi);
   if (e == hipSuccess) e = p.ensure(rdi);
-  if (e == hipSuccess) e = tvec.ensure(2 * (size_t)rdi);
-  if (e == hipSuccess) e = wvec.ensure(2 * (size_t)rdi);
-  if (e == hipSuccess) e = e1buf.ensure(Rnew);
+  if (e == hipSuccess) e = tvec.ensure(3 * (size_t)rdi + 8);
+  if (e == hipSuccess) e = wvec.ensure(3 * (size_t)rdi + 8);
   if (e != hipSuccess) return hipfail(e, "isvd buffers");
-  double *t1 = tvec.p, *t2 = tvec.p + rdi, *w1 = wvec.p, *w2 = wvec.p + rdi;
-  RowMap ident{};
-  ident.nm = m;
-  ident.identity = 1;
-  IsvdArgs ia{};
-  ia.V = V0;
-  ia.ldv = Rnew;
-  ia.r = rdi;
-  ia.R = Rnew;
-  ia.map = ident;
-  ia.d = dvec;
-  ia.p1 = w1;
-  ia.colpart = colpart.p;
-  ia.q2part = q2part.p;
-  ia.e1out = e1buf.p;
+  double *t1 = tvec.p, *t2 = tvec.p + rdi, *ge = tvec.p + 2 * rdi;
+  double *w1 = wvec.p, *w2 = wvec.p + rdi, *ws = wvec.p + 2 * rdi;
+  double *sc = sums.p + 8;  // [0] ||e1||^2, [1] q^2, [2] cancelled magnitude
+  double *dd = sums.p + 12, *ee = sums.p + 13;
   tic();
-  e = launch_isvd_pass(1, ia, nb, stream);
+  e = launch_gemv_t(V0, Rnew, rdi, dvec, colpart.p, nbg, stream);
   if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nb, rdi, t1, nullptr, nullptr, nullptr, nullptr, stream);
-  if (e == hipSuccess) e = launch_small_gemv(M, rdi, t1, 1, p1.p, nullptr, nullptr, stream);
-  if (e == hipSuccess) e = launch_small_gemv(M, rdi, p1.p, 0, w1, nullptr, nullptr, stream);
-  if (e == hipSuccess) e = launch_isvd_pass(2, ia, nb, stream);
+    e = launch_colsum(colpart.p, nbg, rdi, t1, nullptr, nullptr, colpart.p + (size_t)rdi * nbg,
+                      dd, stream);
   if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nb, rdi, t2, nullptr, nullptr, q2part.p, sums.p, stream);
-  if (e == hipSuccess) e = launch_small_gemv(M, rdi, t2, 1, p2.p, p1.p, p.p, stream);
-  // V0 read twice, d read twice, e1 written once (FP64)
-  toc(ST_K_ISVD, 6.0 * Rnew * rdi, 2.0 * 8.0 * Rnew * rdi + 3.0 * 8.0 * Rnew);
+    e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, stream);
+  // V0 and d read once (FP64); r x r products
+  toc(ST_K_ISVD, 2.0 * Rnew * rdi + 10.0 * (double)rdi * rdi, 8.0 * Rnew * (rdi + 1.0));
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin, sums.p, sizeof(double), hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(hpin, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 1, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(hpin + 3, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 1 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
+    e = hipMemcpyAsync(hpin + 3 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
                        stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "isvd projections");
   settle();
-  const double e1sq = hpin[0];
-  double pmax = 0.0, p2max = 0.0, p2sq = 0.0;
-  for (int j = 0; j < rdi; ++j) {
-    pmax = std::max(pmax, std::fabs(hpin[1 + j]));
-    const double v2 = hpin[1 + rdi + j];
-    p2max = std::max(p2max, std::fabs(v2));
-    p2sq += v2 * v2;
-  }
-  q2 = std::max(e1sq - p2sq, 0.0);
-  const double q = std::sqrt(q2);
+  double e1sq = hpin[0];
+  q2 = std::max(hpin[1], 0.0);
+  double q = std::sqrt(q2);
+  // rounding bound of the cancelled sum forming q^2, as a bound on q
+  const double dq2 = 64.0 * 0x1p-53 * hpin[2];
+  const double dq = q > 0.0 ? dq2 / (2.0 * q) : std::sqrt(dq2);
   if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+  if (std::fabs(q - eps) <= 4.0 * dq) {
+    // too close to call from G0: redo the second pass exactly over V0
+    RowMap ident{};
+    ident.nm = m;
+    ident.identity = 1;
+    IsvdArgs ia{};
+    ia.V = V0;
+    ia.ldv = Rnew;
+    ia.r = rdi;
+    ia.R = Rnew;
+    ia.map = ident;
+    ia.d = dvec;
+    ia.p1 = w1;
+    ia.colpart = colpart.p;
+    ia.q2part = q2part.p;
+    tic();
+    e = launch_isvd_pass(2, ia, nbp, stream);
+    if (e == hipSuccess)
+      e = launch_colsum(colpart.p, nbp, rdi, t2, nullptr, nullptr, q2part.p, sc, stream);
+    if (e == hipSuccess)
+      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, stream);
+    toc(ST_K_ISVD, 4.0 * Rnew * rdi, 8.0 * Rnew * (rdi + 1.0));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hpin, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hpin + 3, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hpin + 3 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
+                         stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "exact second pass");
+    settle();
+    e1sq = hpin[0];
+    q2 = std::max(hpin[1], 0.0);
+    q = std::sqrt(q2);
+    ++stt.guard_hits;
+  }
+  double pmax = 0.0, p2max = 0.0;
+  for (int j = 0; j < rdi; ++j) {
+    pmax = std::max(pmax, std::fabs(hpin[3 + j]));
+    p2max = std::max(p2max, std::fabs(hpin[3 + rdi + j]));
+  }
   const double tol = 8.0 * 0x1p-53 * std::max({S_host.empty() ? 0.0 : S_host[0], pmax, q});
   grow = (q > eps && q > tol) ? 1 : 0;
   c = rd + grow;
@@ -906,6 +943,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   if (e == hipSuccess) e = V2.ensure((size_t)nn * c);
   if (e == hipSuccess) e = S[nxt].ensure(c);
   if (e == hipSuccess) e = Mf[nxt].ensure((size_t)(c * c));
+  if (e == hipSuccess) e = Gf[nxt].ensure((size_t)(c * c));
   int64_t ldn = ud_ld[nxt];
   if (e == hipSuccess && (ldn < nd + 1 || Ud[nxt].cap < (size_t)ldn * c)) {
     ldn = std::max<int64_t>(ud_ld[cur], round_up(nd + 1, 64));
@@ -920,15 +958,33 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   if (e != hipSuccess) return hipfail(e, "small SVD");
   tic();
   if (grow) {
-    // v = (e1 - V0 M p2) / q into column r_d of V0
-    e = launch_small_gemv(M, rdi, p2.p, 0, w2, nullptr, nullptr, stream);
+    // e = d - V0 (w1 + w2) into column r_d of V0 with V0^T e and ||e||^2 in one
+    // sweep; then v = e / q and G0 gains a row and column
+    RowMap ident{};
+    ident.nm = m;
+    ident.identity = 1;
+    IsvdArgs ia{};
+    ia.V = V0;
+    ia.ldv = Rnew;
+    ia.r = rdi;
+    ia.R = Rnew;
+    ia.map = ident;
+    ia.d = dvec;
+    ia.p1 = ws;
+    ia.colpart = colpart.p;
+    ia.q2part = q2part.p;
+    ia.e1out = V0 + Rnew * rd;
+    e = launch_isvd_pass(2, ia, nbp, stream);
     if (e == hipSuccess)
-      e = launch_vcol(V0, Rnew, rdi, w2, e1buf.p, 1.0 / q, V0 + Rnew * rd, nullptr, stream);
+      e = launch_colsum(colpart.p, nbp, rdi, ge, nullptr, nullptr, q2part.p, ee, stream);
+    if (e == hipSuccess) e = launch_scale(V0 + Rnew * rd, Rnew, 1.0 / q, stream);
   }
+  if (e == hipSuccess)
+    e = launch_g0_update(G0, rdi, ge, ee, grow ? 1.0 / q : 0.0, grow, Gf[nxt].p, stream);
   if (e == hipSuccess) e = launch_m_update(M, rdi, V2.p, (int)c, grow, Mf[nxt].p, stream);
-  // the appended column: read V0 and e1, write one column; M~: c^2 r flops
-  toc(ST_K_ROT_V, (grow ? 2.0 * Rnew * rd : 0.0) + 2.0 * (double)c * c * rd,
-      grow ? 8.0 * ((double)Rnew * rd + 2.0 * Rnew) : 8.0 * (double)c * c);
+  // the appended column: V0 and d read, one column written; M~: c^2 r flops
+  toc(ST_K_ROT_V, (grow ? 4.0 * Rnew * rd : 0.0) + 2.0 * (double)c * c * rd,
+      grow ? 8.0 * ((double)Rnew * rd + 3.0 * Rnew) : 16.0 * (double)c * c);
   if (e != hipSuccess) return hipfail(e, "V0 / M update");
   tic();
   e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
@@ -1042,6 +1098,7 @@ void st_handle::destroy() {
     S[i].release();
     V[i].release();
     Mf[i].release();
+    Gf[i].release();
     C[i].release();
     D[i].release();
     RB[i].release();

@@ -279,9 +279,11 @@ hipError_t launch_secular_svd(SecData s, const double *S, const double *p, doubl
   hipLaunchKernelGGL(sec_roots_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   hipLaunchKernelGGL(sec_zhat_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   const size_t lds = 2 * (size_t)n * sizeof(double);
-  if (lds > 64 * 1024)
-    hipFuncSetAttribute((const void *)sec_vec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(
+        (const void *)sec_vec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(sec_vec_kernel, dim3(ntrip), dim3(64), lds, st, s, ntrip, U2, V2, Snew);
   return hipGetLastError();
 }
@@ -667,6 +669,179 @@ hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, cons
   if (rd <= 0) return hipSuccess;
   hipLaunchKernelGGL(ud_row64_kernel, dim3((unsigned)((rd + 63) / 64)), dim3(64), 0, s, Ud, ld, t,
                      rd, S, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// V0^T x for a tall column-major V0 (R x r): lanes run over rows (coalesced
+// column segments, no LDS), each lane keeps its RPL entries of x in registers,
+// and the four waves of a block split the columns. Block b covers rows
+// [64 RPL b, 64 RPL (b + 1)) and writes part[j * nb + b] (j < r) and
+// part[r * nb + b] = sum of x^2 over its rows.
+// ---------------------------------------------------------------------------
+constexpr int kGemvRPL = 8;
+
+__global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t R, int r,
+                                                     const double *x, double *part) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nb = gridDim.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 * kGemvRPL + lane;
+  const bool full = (int64_t)(blockIdx.x + 1) * 64 * kGemvRPL <= R;
+  double xv[kGemvRPL];
+  double xx = 0.0;
+#pragma unroll
+  for (int i = 0; i < kGemvRPL; ++i) {
+    const int64_t row = row0 + 64 * i;
+    xv[i] = row < R ? x[row] : 0.0;
+    xx += xv[i] * xv[i];
+  }
+  for (int j = wid; j < r; j += 4) {
+    const double *col = V0 + R * (int64_t)j;
+    double s = 0.0;
+    if (full) {
+#pragma unroll
+      for (int i = 0; i < kGemvRPL; ++i) s += col[row0 + 64 * i] * xv[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < kGemvRPL; ++i) {
+        const int64_t row = row0 + 64 * i;
+        if (row < R) s += col[row] * xv[i];
+      }
+    }
+    s = wave_sum(s);
+    if (lane == 0) part[(size_t)j * nb + blockIdx.x] = s;
+  }
+  if (wid == 0) {
+    xx = wave_sum(xx);
+    if (lane == 0) part[(size_t)r * nb + blockIdx.x] = xx;
+  }
+}
+
+int gemv_t_blocks(int64_t R) {
+  const int64_t t = (R + 64 * kGemvRPL - 1) / (64 * kGemvRPL);
+  return (int)(t > 0 ? t : 1);
+}
+
+hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, double *part,
+                         int nb, hipStream_t s) {
+  hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)nb), dim3(256), 0, s, V0, R, r, x, part);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The r x r part of the two Gram-Schmidt passes in the factored form, with
+// G0 = V0^T V0 kept up to date so the second pass needs no sweep over V0:
+//   p1 = M^T t1, w1 = M p1, t2 = t1 - G0 w1          (t2 = V0^T e1)
+//   ||e1||^2 = ||d||^2 - 2 w1.t1 + w1.G0 w1
+//   p2 = M^T t2, w2 = M p2, p = p1 + p2, ws = w1 + w2
+//   q^2 = ||e1||^2 - 2 w2.t2 + w2.G0 w2              (e = e1 - V0 w2)
+// With `given`, t2 and ||e1||^2 (sc[0]) come from an exact sweep instead.
+// sc: [0] ||e1||^2, [1] q^2, [2] magnitude of the terms cancelled in q^2.
+// One block; r x r products split over its threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void isvd_gram_kernel(const double *M, const double *G0, int r,
+                                                        const double *t1, const double *dd,
+                                                        int given, double *p1, double *w1,
+                                                        double *t2, double *p2, double *w2,
+                                                        double *p, double *ws, double *sc) {
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < r; i += blockDim.x) {
+    double a = 0.0;
+    for (int l = 0; l < r; ++l) a += M[l + (size_t)r * i] * t1[l];
+    p1[i] = a;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += blockDim.x) {
+    double a = 0.0;
+    for (int l = 0; l < r; ++l) a += M[i + (size_t)r * l] * p1[l];
+    w1[i] = a;
+  }
+  __syncthreads();
+  double a1 = 0.0, a2 = 0.0;
+  for (int i = tid; i < r; i += blockDim.x) {
+    double g = 0.0;
+    for (int l = 0; l < r; ++l) g += G0[i + (size_t)r * l] * w1[l];
+    if (!given) t2[i] = t1[i] - g;
+    a1 += w1[i] * t1[i];
+    a2 += w1[i] * g;
+  }
+  a1 = block_sum(a1, red);
+  a2 = block_sum(a2, red);
+  const double e1sq = given ? sc[0] : dd[0] - 2.0 * a1 + a2;
+  __syncthreads();
+  for (int i = tid; i < r; i += blockDim.x) {
+    double a = 0.0;
+    for (int l = 0; l < r; ++l) a += M[l + (size_t)r * i] * t2[l];
+    p2[i] = a;
+    p[i] = p1[i] + a;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += blockDim.x) {
+    double a = 0.0;
+    for (int l = 0; l < r; ++l) a += M[i + (size_t)r * l] * p2[l];
+    w2[i] = a;
+    ws[i] = w1[i] + a;
+  }
+  __syncthreads();
+  double b1 = 0.0, b2 = 0.0;
+  for (int i = tid; i < r; i += blockDim.x) {
+    double g = 0.0;
+    for (int l = 0; l < r; ++l) g += G0[i + (size_t)r * l] * w2[l];
+    b1 += w2[i] * t2[i];
+    b2 += w2[i] * g;
+  }
+  b1 = block_sum(b1, red);
+  b2 = block_sum(b2, red);
+  if (tid == 0) {
+    sc[0] = e1sq;
+    sc[1] = e1sq - 2.0 * b1 + b2;
+    sc[2] = (given ? e1sq : dd[0] + 2.0 * fabs(a1) + fabs(a2)) + 2.0 * fabs(b1) + fabs(b2);
+  }
+}
+
+hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const double *t1,
+                            const double *dd, int given, double *p1, double *w1, double *t2,
+                            double *p2, double *w2, double *p, double *ws, double *sc,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(isvd_gram_kernel, dim3(1), dim3(256), 0, s, M, G0, r, t1, dd, given, p1, w1,
+                     t2, p2, w2, p, ws, sc);
+  return hipGetLastError();
+}
+
+// Gn ((r + 1) x (r + 1)) = [[G0, g / q], [g^T / q, ee / q^2]] after appending
+// v = e / q to V0 (g = V0^T e, ee = ||e||^2); or Gn = G0 (grow = 0).
+__global__ void g0_update_kernel(const double *G0, int r, const double *g, const double *ee,
+                                 double inv_q, int grow, double *Gn) {
+  const int c = r + grow;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  const int i = idx % c, j = idx / c;
+  double v;
+  if (i < r && j < r) v = G0[i + (size_t)r * j];
+  else if (i < r) v = g[i] * inv_q;
+  else if (j < r) v = g[j] * inv_q;
+  else v = ee[0] * inv_q * inv_q;
+  Gn[i + (size_t)c * j] = v;
+}
+
+hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
+                            double inv_q, int grow, double *Gn, hipStream_t s) {
+  const int c = r + grow;
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(g0_update_kernel, dim3((unsigned)((c * c + 255) / 256)), dim3(256), 0, s,
+                     G0, r, g, ee, inv_q, grow, Gn);
+  return hipGetLastError();
+}
+
+__global__ void scale_kernel(double *x, int64_t n, double a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= a;
+}
+
+hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, a);
   return hipGetLastError();
 }
 

@@ -74,6 +74,19 @@ hipError_t launch_identity(double *M, int n, hipStream_t s);
 hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, const double *S,
                            double *out, hipStream_t s);
 
+// V0^T x partials (rows split over blocks, see k_isvd.hip) and the r x r part
+// of the two Gram-Schmidt passes with G0 = V0^T V0 maintained.
+int gemv_t_blocks(int64_t R);
+hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, double *part,
+                         int nb, hipStream_t s);
+hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const double *t1,
+                            const double *dd, int given, double *p1, double *w1, double *t2,
+                            double *p2, double *w2, double *p, double *ws, double *sc,
+                            hipStream_t s);
+hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
+                            double inv_q, int grow, double *Gn, hipStream_t s);
+hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s);
+
 // Message for st_last_error(NULL) after a failed stateless call.
 void set_stateless_error(const char *msg);
 
