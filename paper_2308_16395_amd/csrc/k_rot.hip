@@ -50,27 +50,67 @@ __global__ __launch_bounds__(kThreads) void rot_kernel(FiberIn in, const T *w, i
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) dot[nt] = 0.0;
 
-  for (int64_t kb = 0; kb < K; kb += 32) {
-    // stage W[mbeg .. mbeg + 16 MT)[kb .. kb + 32) in LDS
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < MT * 16 * 32; idx += kThreads) {
+  // Software pipeline: the W slice and the X values of K block kb + 32 are
+  // loaded into registers while the MFMAs consume block kb (W from LDS).
+  constexpr int WPT = MT * 16 * 32 / kThreads;  // W elements staged per thread
+  T wreg[WPT];
+  double xreg[NT][8];
+  auto load_w = [&](int64_t kb) {
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int idx = threadIdx.x + kThreads * q;
       const int r = idx >> 5, c = idx & 31;
       const int64_t m = mbeg + r, k = kb + c;
-      ws[r * LDW + c] = (m < mend && k < K) ? w[m * ldw + k] : (T)0;
+      wreg[q] = (m < mend && k < K) ? w[m * ldw + k] : (T)0;
     }
-    __syncthreads();
-    const int64_t k0 = kb + 8 * grp;
-    double xd[NT][8];
+  };
+  auto load_x = [&](int64_t kb) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const int64_t k = k0 + s;
-        double x = 0.0;
-        if (k < n && base[nt] >= 0) x = (double)xp[base[nt] + in.a * k];
-        if (EXTRA == 2 && k < n) dot[nt] += x * pvec[k];
-        xd[nt][s] = x;
+        const int64_t k = kb + 4 * s + grp;
+        xreg[nt][s] = (k < n && base[nt] >= 0) ? (double)xp[base[nt] + in.a * k] : 0.0;
       }
+  };
+  // FP64 state: prefetch one block ahead. The FP32 core keeps the loads in
+  // the iteration (its lower register use allows two waves per SIMD instead).
+  constexpr bool kPipe = std::is_same<T, double>::value;
+  if constexpr (kPipe) {
+    load_w(0);
+    load_x(0);
+  }
+  for (int64_t kb = 0; kb < K; kb += 32) {
+    __syncthreads();  // the previous block's LDS reads are done
+    if constexpr (!kPipe) {
+      load_w(kb);
+      load_x(kb);
+    }
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int idx = threadIdx.x + kThreads * q;
+      ws[(idx >> 5) * LDW + (idx & 31)] = wreg[q];
+    }
+    double xd[NT][8];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) xd[nt][s] = xreg[nt][s];
+    __syncthreads();
+    if constexpr (kPipe) {
+      if (kb + 32 < K) {
+        load_w(kb + 32);
+        load_x(kb + 32);
+      }
+    }
+    if (EXTRA == 2) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int64_t k = kb + 4 * s + grp;
+          if (k < n) dot[nt] += xd[nt][s] * pvec[k];
+        }
     }
     if (EXTRA && kb + 32 > n) {  // the block holding element n
       const int sl = (int)(n - kb);
@@ -86,21 +126,26 @@ __global__ __launch_bounds__(kThreads) void rot_kernel(FiberIn in, const T *w, i
         } else if (fib[nt] < in.F) {
           ev = in.extra[fib[nt]];
         }
-        if (grp == (sl >> 3)) {
+        if (grp == (sl & 3)) {
 #pragma unroll
           for (int s = 0; s < 8; ++s)
-            if (s == (sl & 7)) xd[nt][s] = ev;
+            if (s == (sl >> 2)) xd[nt][s] = ev;
         }
       }
     }
+    // MFMA s covers k = kb + 4 s .. kb + 4 s + 3 (lane group grp holds k = kb + 4 s + grp);
+    // steps wholly past K (the tail of the last block) are skipped
+    const int steps = (int)((K - kb + 3) / 4 < 8 ? (K - kb + 3) / 4 : 8);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      const T *wr = ws + (16 * mt + col) * LDW + 8 * grp;
+      const T *wr = ws + (16 * mt + col) * LDW + grp;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const double a = (double)wr[s];
+        if (s < steps) {
+          const double a = (double)wr[4 * s];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a, xd[nt][s], acc[mt][nt]);
+          for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a, xd[nt][s], acc[mt][nt]);
+        }
       }
     }
   }
@@ -148,13 +193,19 @@ template <class T>
 hipError_t launch_rot_typed(const FiberIn &in, const T *w, int64_t ldw, int m0, int mcount,
                             const FiberOut &out, int extra_mode, const double *pvec,
                             hipStream_t s) {
+  // the smallest instantiated column-tile count that covers mcount (padding
+  // columns cost whole MFMAs); wider outputs take several column blocks
   const int tiles = (mcount + 15) / 16;
-  if (tiles <= 2) return launch_rot_t<2, 2, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
-  if (tiles <= 4) return launch_rot_t<4, 2, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
-  if (tiles <= 6) return launch_rot_t<6, 2, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
-  if (tiles <= 8) return launch_rot_t<8, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
-  if (tiles <= 10)
-    return launch_rot_t<10, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+#define ST_ROT_CASE(T_, NT_) \
+  if (tiles <= T_) return launch_rot_t<T_, NT_, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+  ST_ROT_CASE(2, 2)
+  ST_ROT_CASE(4, 2)
+  ST_ROT_CASE(6, 2)
+  ST_ROT_CASE(8, 1)
+  ST_ROT_CASE(9, 1)
+  ST_ROT_CASE(10, 1)
+  ST_ROT_CASE(11, 1)
+#undef ST_ROT_CASE
   return launch_rot_t<12, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
 }
 
