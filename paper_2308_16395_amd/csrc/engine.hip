@@ -853,10 +853,10 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   if (e == hipSuccess) e = p2.ensure(rdi);
   if (e == hipSuccess) e = p.ensure(rdi);
   if (e == hipSuccess) e = tvec.ensure(3 * (size_t)rdi + 8);
-  if (e == hipSuccess) e = wvec.ensure(3 * (size_t)rdi + 8);
+  if (e == hipSuccess) e = wvec.ensure(4 * (size_t)rdi + 8);
   if (e != hipSuccess) return hipfail(e, "isvd buffers");
   double *t1 = tvec.p, *t2 = tvec.p + rdi, *ge = tvec.p + 2 * rdi;
-  double *w1 = wvec.p, *w2 = wvec.p + rdi, *ws = wvec.p + 2 * rdi;
+  double *w1 = wvec.p, *w2 = wvec.p + rdi, *ws = wvec.p + 2 * rdi, *gv = wvec.p + 3 * rdi;
   double *sc = sums.p + 8;  // [0] ||e1||^2, [1] q^2, [2] cancelled magnitude
   double *dd = sums.p + 12, *ee = sums.p + 13;
   tic();
@@ -865,7 +865,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
     e = launch_colsum(colpart.p, nbg, rdi, t1, nullptr, nullptr, colpart.p + (size_t)rdi * nbg,
                       dd, stream);
   if (e == hipSuccess)
-    e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, stream);
+    e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, stream);
   // V0 and d read once (FP64); r x r products
   toc(ST_K_ISVD, 2.0 * Rnew * rdi + 10.0 * (double)rdi * rdi, 8.0 * Rnew * (rdi + 1.0));
   if (e == hipSuccess)
@@ -905,7 +905,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
     if (e == hipSuccess)
       e = launch_colsum(colpart.p, nbp, rdi, t2, nullptr, nullptr, q2part.p, sc, stream);
     if (e == hipSuccess)
-      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, stream);
+      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, stream);
     toc(ST_K_ISVD, 4.0 * Rnew * rdi, 8.0 * Rnew * (rdi + 1.0));
     if (e == hipSuccess)
       e = hipMemcpyAsync(hpin, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);

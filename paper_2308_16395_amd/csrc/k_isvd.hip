@@ -214,9 +214,91 @@ struct WaveRed {
   }
 };
 
-__global__ void sec_prep_kernel(SecData s, const double *S, const double *p, double q, int grow,
-                                double tol) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) sec_prep(s, S, p, q, grow, tol);
+// The preparation of sec_prep in parallel on one block: poles and weights,
+// active flags, the (rare) rotations of poles closer than tol -- done by one
+// thread exactly as sec_prep does, and only when some adjacent poles are that
+// close -- and the ordered lists of active and deflated indices by ballot
+// prefix sums. zz is summed in the block's fixed order.
+__global__ __launch_bounds__(256) void sec_prep_kernel(SecData s, const double *S, const double *p,
+                                                       double q, int grow, double tol) {
+  __shared__ int close_pair;
+  __shared__ int wcount[2][4];
+  __shared__ double red[16];
+  const int r = s.r, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int t = tid; t <= r; t += blockDim.x) {
+    if (t == 0) {
+      s.d[0] = 0.0;
+      s.z[0] = grow ? q : 0.0;
+      s.active[0] = grow ? 1 : 0;
+    } else {
+      const double z = p[r - t];
+      s.d[t] = S[r - t];
+      s.z[t] = z;
+      s.active[t] = fabs(z) > tol ? 1 : 0;
+    }
+  }
+  if (tid == 0) close_pair = 0;
+  __syncthreads();
+  for (int t = 2 + tid; t <= r; t += blockDim.x)
+    if (s.d[t] - s.d[t - 1] <= tol) close_pair = 1;
+  __syncthreads();
+  if (tid == 0) {
+    int nrot = 0;
+    if (close_pair) {
+      int prev = -1;
+      for (int t = 1; t <= r; ++t) {
+        if (!s.active[t]) continue;
+        if (prev >= 1 && s.d[t] - s.d[prev] <= tol) {
+          const double za = s.z[prev], zb = s.z[t];
+          const double rho = hypot(za, zb);
+          s.z[t] = rho;
+          s.z[prev] = 0.0;
+          s.active[prev] = 0;
+          s.rot_t[2 * nrot] = prev;
+          s.rot_t[2 * nrot + 1] = t;
+          s.rot_cs[2 * nrot] = zb / rho;
+          s.rot_cs[2 * nrot + 1] = za / rho;
+          ++nrot;
+        }
+        prev = t;
+      }
+    }
+    s.counts[2] = nrot;
+  }
+  __syncthreads();
+  int mK = 0, mD = 0;
+  double zz = 0.0;
+  for (int base = 0; base <= r; base += blockDim.x) {
+    const int t = base + tid;
+    const int act = (t <= r) ? s.active[t] : 0;
+    const int dfl = (t >= 1 && t <= r && !act) ? 1 : 0;
+    if (act) zz += s.z[t] * s.z[t];
+    const unsigned long long ma = __ballot(act), md = __ballot(dfl);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) {
+      wcount[0][wid] = __popcll(ma);
+      wcount[1][wid] = __popcll(md);
+    }
+    __syncthreads();
+    int offK = mK, offD = mD;
+    for (int w = 0; w < wid; ++w) {
+      offK += wcount[0][w];
+      offD += wcount[1][w];
+    }
+    if (act) s.K[offK + __popcll(ma & below)] = t;
+    if (dfl) s.defl[offD + __popcll(md & below)] = t;
+    for (int w = 0; w < 4; ++w) {
+      mK += wcount[0][w];
+      mD += wcount[1][w];
+    }
+    __syncthreads();
+  }
+  zz = block_sum(zz, red);
+  if (tid == 0) {
+    s.counts[0] = mK;
+    s.counts[1] = mD;
+    s.zz[0] = zz;
+  }
 }
 
 __global__ __launch_bounds__(256) void sec_roots_kernel(SecData s) {
@@ -275,7 +357,7 @@ hipError_t launch_secular_svd(SecData s, const double *S, const double *p, doubl
                               hipStream_t st) {
   const int n = s.n;
   hipLaunchKernelGGL(sec_zero_zh_kernel, dim3((n + 255) / 256), dim3(256), 0, st, s);
-  hipLaunchKernelGGL(sec_prep_kernel, dim3(1), dim3(64), 0, st, s, S, p, q, grow, tol);
+  hipLaunchKernelGGL(sec_prep_kernel, dim3(1), dim3(256), 0, st, s, S, p, q, grow, tol);
   hipLaunchKernelGGL(sec_roots_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   hipLaunchKernelGGL(sec_zhat_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   const size_t lds = 2 * (size_t)n * sizeof(double);
@@ -302,6 +384,7 @@ __global__ void ud_update_kernel(const double *Ud, int64_t ldo, int64_t nd, int 
   double s;
   if (row < nd) {
     s = 0.0;
+#pragma unroll 8
     for (int k = 0; k < r; ++k) s += Ud[row + ldo * k] * u2c[k];
   } else {
     s = u2c[r];
@@ -587,6 +670,7 @@ __global__ void m_update_kernel(const double *M, int r, const double *V2, int c,
   double acc;
   if (i < r) {
     acc = 0.0;
+#pragma unroll 8
     for (int l = 0; l < r; ++l) acc += M[i + (size_t)r * l] * v2c[l];
   } else {  // grow: the appended direction of blockdiag(M, 1)
     acc = grow ? v2c[r] : 0.0;
@@ -739,57 +823,63 @@ hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, do
 // sc: [0] ||e1||^2, [1] q^2, [2] magnitude of the terms cancelled in q^2.
 // One block; r x r products split over its threads.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void isvd_gram_kernel(const double *M, const double *G0, int r,
-                                                        const double *t1, const double *dd,
-                                                        int given, double *p1, double *w1,
-                                                        double *t2, double *p2, double *w2,
-                                                        double *p, double *ws, double *sc) {
+// y = M^T x: one wave per output, lanes along the (contiguous) column of M
+__device__ inline void mv_trans(const double *M, int r, const double *x, double *y) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wid; i < r; i += nw) {
+    const double *mc = M + (size_t)r * i;
+    double a = 0.0;
+    for (int l = lane; l < r; l += 64) a += mc[l] * x[l];
+    a = wave_sum(a);
+    if (lane == 0) y[i] = a;
+  }
+}
+
+// y = M x: one thread per output, consecutive threads on consecutive rows
+__device__ inline void mv_plain(const double *M, int r, const double *x, double *y) {
+  for (int i = threadIdx.x; i < r; i += blockDim.x) {
+    double a = 0.0;
+    for (int l = 0; l < r; ++l) a += M[i + (size_t)r * l] * x[l];
+    y[i] = a;
+  }
+}
+
+__global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const double *G0, int r,
+                                                         const double *t1, const double *dd,
+                                                         int given, double *p1, double *w1,
+                                                         double *t2, double *p2, double *w2,
+                                                         double *p, double *ws, double *sc,
+                                                         double *g) {
   __shared__ double red[16];
   const int tid = threadIdx.x;
-  for (int i = tid; i < r; i += blockDim.x) {
-    double a = 0.0;
-    for (int l = 0; l < r; ++l) a += M[l + (size_t)r * i] * t1[l];
-    p1[i] = a;
-  }
+  mv_trans(M, r, t1, p1);
   __syncthreads();
-  for (int i = tid; i < r; i += blockDim.x) {
-    double a = 0.0;
-    for (int l = 0; l < r; ++l) a += M[i + (size_t)r * l] * p1[l];
-    w1[i] = a;
-  }
+  mv_plain(M, r, p1, w1);
+  __syncthreads();
+  mv_plain(G0, r, w1, g);  // G0 is symmetric
   __syncthreads();
   double a1 = 0.0, a2 = 0.0;
   for (int i = tid; i < r; i += blockDim.x) {
-    double g = 0.0;
-    for (int l = 0; l < r; ++l) g += G0[i + (size_t)r * l] * w1[l];
-    if (!given) t2[i] = t1[i] - g;
+    if (!given) t2[i] = t1[i] - g[i];
     a1 += w1[i] * t1[i];
-    a2 += w1[i] * g;
+    a2 += w1[i] * g[i];
   }
   a1 = block_sum(a1, red);
   a2 = block_sum(a2, red);
   const double e1sq = given ? sc[0] : dd[0] - 2.0 * a1 + a2;
   __syncthreads();
-  for (int i = tid; i < r; i += blockDim.x) {
-    double a = 0.0;
-    for (int l = 0; l < r; ++l) a += M[l + (size_t)r * i] * t2[l];
-    p2[i] = a;
-    p[i] = p1[i] + a;
-  }
+  mv_trans(M, r, t2, p2);
   __syncthreads();
-  for (int i = tid; i < r; i += blockDim.x) {
-    double a = 0.0;
-    for (int l = 0; l < r; ++l) a += M[i + (size_t)r * l] * p2[l];
-    w2[i] = a;
-    ws[i] = w1[i] + a;
-  }
+  for (int i = tid; i < r; i += blockDim.x) p[i] = p1[i] + p2[i];
+  mv_plain(M, r, p2, w2);
+  __syncthreads();
+  mv_plain(G0, r, w2, g);
   __syncthreads();
   double b1 = 0.0, b2 = 0.0;
   for (int i = tid; i < r; i += blockDim.x) {
-    double g = 0.0;
-    for (int l = 0; l < r; ++l) g += G0[i + (size_t)r * l] * w2[l];
+    ws[i] = w1[i] + w2[i];
     b1 += w2[i] * t2[i];
-    b2 += w2[i] * g;
+    b2 += w2[i] * g[i];
   }
   b1 = block_sum(b1, red);
   b2 = block_sum(b2, red);
@@ -803,9 +893,9 @@ __global__ __launch_bounds__(256) void isvd_gram_kernel(const double *M, const d
 hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const double *t1,
                             const double *dd, int given, double *p1, double *w1, double *t2,
                             double *p2, double *w2, double *p, double *ws, double *sc,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(isvd_gram_kernel, dim3(1), dim3(256), 0, s, M, G0, r, t1, dd, given, p1, w1,
-                     t2, p2, w2, p, ws, sc);
+                            double *g, hipStream_t s) {
+  hipLaunchKernelGGL(isvd_gram_kernel, dim3(1), dim3(1024), 0, s, M, G0, r, t1, dd, given, p1,
+                     w1, t2, p2, w2, p, ws, sc, g);
   return hipGetLastError();
 }
 

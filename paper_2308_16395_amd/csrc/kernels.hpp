@@ -82,7 +82,7 @@ hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, do
 hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const double *t1,
                             const double *dd, int given, double *p1, double *w1, double *t2,
                             double *p2, double *w2, double *p, double *ws, double *sc,
-                            hipStream_t s);
+                            double *g, hipStream_t s);
 hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
                             double inv_q, int grow, double *Gn, hipStream_t s);
 hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s);
