@@ -658,13 +658,16 @@ int st_handle::do_update(const float *y) {
     return ST_OK;
   }
   const int rdi = (int)rd;
-  const int nb = isvd_blocks(Rnew);
-  e = colpart.ensure((size_t)nb * rdi);
-  if (e == hipSuccess) e = q2part.ensure(nb);
+  // Alg. 3's two Gram-Schmidt passes: p1 = V^T d by a coalesced GEMV (V read
+  // through the row map), then one sweep forming e1 = d - V p1 with ||e1||^2 and
+  // p2 = V^T e1; p = p1 + p2 and q^2 = ||e1||^2 - ||p2||^2
+  const int nbg = gemv_t_blocks(Rnew);
+  const int nbp = isvd_blocks(Rnew);
+  e = colpart.ensure((size_t)(rdi + 1) * std::max(nbg, nbp));
+  if (e == hipSuccess) e = q2part.ensure(nbp);
   if (e == hipSuccess) e = p1.ensure(rdi);
   if (e == hipSuccess) e = p2.ensure(rdi);
   if (e == hipSuccess) e = p.ensure(rdi);
-
   if (e != hipSuccess) return hipfail(e, "isvd buffers");
   IsvdArgs ia{};
   ia.V = V[cur].p;
@@ -677,37 +680,36 @@ int st_handle::do_update(const float *y) {
   ia.colpart = colpart.p;
   ia.q2part = q2part.p;
   tic();
-  // p1 = V^T d; e1 = d - V p1, ||e1||^2, p2 = V^T e1; p = p1 + p2
-  e = launch_isvd_pass(1, ia, nb, stream);
+  e = launch_gemv_t_mapped(V[cur].p, Rold, map, Rnew, rdi, dvec, colpart.p, nbg, stream);
   if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nb, rdi, p1.p, nullptr, nullptr, nullptr, nullptr, stream);
-  if (e == hipSuccess) e = launch_isvd_pass(2, ia, nb, stream);
+    e = launch_colsum(colpart.p, nbg, rdi, p1.p, nullptr, nullptr, nullptr, nullptr, stream);
+  if (e == hipSuccess) e = launch_isvd_pass(2, ia, nbp, stream);
   if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nb, rdi, p2.p, p1.p, p.p, q2part.p, sums.p, stream);
-  // 4 R r flops (two passes of V^T x) + 2 R r (row dots); V (FP64) read twice, d twice
+    e = launch_colsum(colpart.p, nbp, rdi, p2.p, p1.p, p.p, q2part.p, sums.p, stream);
+  // 4 R r flops (two products with V^T) + 2 R r (row dots); V (FP64) read twice, d twice
   toc(ST_K_ISVD, 6.0 * Rnew * rdi, 2.0 * 8.0 * Rold * rdi + 2.0 * 8.0 * Rnew);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hpin, sums.p, sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 1, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(hpin + 3, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 1 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
+    e = hipMemcpyAsync(hpin + 3 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
                        stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "isvd projections");
   settle();
   // q^2 = ||e1 - V p2||^2 = ||e1||^2 - ||p2||^2 (V orthonormal; p2 ~ u ||d||)
   const double e1sq = hpin[0];
-  double pmax = 0.0, p2max = 0.0, p2sq = 0.0;
-  for (int j = 0; j < rdi; ++j) {
-    pmax = std::max(pmax, std::fabs(hpin[1 + j]));
-    const double v2 = hpin[1 + rdi + j];
-    p2max = std::max(p2max, std::fabs(v2));
-    p2sq += v2 * v2;
-  }
+  double p2sq = 0.0;
+  for (int j = 0; j < rdi; ++j) p2sq += hpin[3 + rdi + j] * hpin[3 + rdi + j];
   const double q2 = std::max(e1sq - p2sq, 0.0);
   const double q = std::sqrt(q2);
   if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+  double pmax = 0.0, p2max = 0.0;
+  for (int j = 0; j < rdi; ++j) {
+    pmax = std::max(pmax, std::fabs(hpin[3 + j]));
+    p2max = std::max(p2max, std::fabs(hpin[3 + rdi + j]));
+  }
   const double tol = 8.0 * 0x1p-53 * std::max({S_host.empty() ? 0.0 : S_host[0], pmax, q});
   const int grow = (q > eps && q > tol) ? 1 : 0;
   const int64_t c = rd + grow;
@@ -865,7 +867,8 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
     e = launch_colsum(colpart.p, nbg, rdi, t1, nullptr, nullptr, colpart.p + (size_t)rdi * nbg,
                       dd, stream);
   if (e == hipSuccess)
-    e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, stream);
+    e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, nullptr,
+                         stream);
   // V0 and d read once (FP64); r x r products
   toc(ST_K_ISVD, 2.0 * Rnew * rdi + 10.0 * (double)rdi * rdi, 8.0 * Rnew * (rdi + 1.0));
   if (e == hipSuccess)
@@ -905,7 +908,8 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
     if (e == hipSuccess)
       e = launch_colsum(colpart.p, nbp, rdi, t2, nullptr, nullptr, q2part.p, sc, stream);
     if (e == hipSuccess)
-      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, stream);
+      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv,
+                           nullptr, stream);
     toc(ST_K_ISVD, 4.0 * Rnew * rdi, 8.0 * Rnew * (rdi + 1.0));
     if (e == hipSuccess)
       e = hipMemcpyAsync(hpin, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);

@@ -765,32 +765,36 @@ hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, cons
 // ---------------------------------------------------------------------------
 constexpr int kGemvRPL = 8;
 
-__global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t R, int r,
-                                                     const double *x, double *part) {
+// MAPPED: V0 is stored at the old ranks (ld = ldv rows) and row i of the new
+// layout reads old row map(i), or is zero for a padded row.
+template <bool MAPPED>
+__global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t ldv, RowMap map,
+                                                     int64_t R, int r, const double *x,
+                                                     double *part) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nb = gridDim.x;
   const int64_t row0 = (int64_t)blockIdx.x * 64 * kGemvRPL + lane;
-  const bool full = (int64_t)(blockIdx.x + 1) * 64 * kGemvRPL <= R;
+  const bool full = !MAPPED && (int64_t)(blockIdx.x + 1) * 64 * kGemvRPL <= R;
   double xv[kGemvRPL];
+  int64_t src[kGemvRPL];
   double xx = 0.0;
 #pragma unroll
   for (int i = 0; i < kGemvRPL; ++i) {
     const int64_t row = row0 + 64 * i;
     xv[i] = row < R ? x[row] : 0.0;
     xx += xv[i] * xv[i];
+    src[i] = row < R ? (MAPPED ? map_new_to_old(map, row) : row) : -1;
   }
   for (int j = wid; j < r; j += 4) {
-    const double *col = V0 + R * (int64_t)j;
+    const double *col = V0 + ldv * (int64_t)j;
     double s = 0.0;
     if (full) {
 #pragma unroll
       for (int i = 0; i < kGemvRPL; ++i) s += col[row0 + 64 * i] * xv[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < kGemvRPL; ++i) {
-        const int64_t row = row0 + 64 * i;
-        if (row < R) s += col[row] * xv[i];
-      }
+      for (int i = 0; i < kGemvRPL; ++i)
+        if (src[i] >= 0) s += col[src[i]] * xv[i];
     }
     s = wave_sum(s);
     if (lane == 0) part[(size_t)j * nb + blockIdx.x] = s;
@@ -808,7 +812,18 @@ int gemv_t_blocks(int64_t R) {
 
 hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, double *part,
                          int nb, hipStream_t s) {
-  hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)nb), dim3(256), 0, s, V0, R, r, x, part);
+  RowMap ident{};
+  ident.identity = 1;
+  hipLaunchKernelGGL(gemv_t_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, V0, R, ident, R,
+                     r, x, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_t_mapped(const double *V, int64_t ldv, const RowMap &map, int64_t R, int r,
+                                const double *x, double *part, int nb, hipStream_t s) {
+  if (map.identity) return launch_gemv_t(V, R, r, x, part, nb, s);
+  hipLaunchKernelGGL(gemv_t_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, V, ldv, map, R, r,
+                     x, part);
   return hipGetLastError();
 }
 
@@ -824,7 +839,12 @@ hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, do
 // One block; r x r products split over its threads.
 // ---------------------------------------------------------------------------
 // y = M^T x: one wave per output, lanes along the (contiguous) column of M
+// (M null: the identity)
 __device__ inline void mv_trans(const double *M, int r, const double *x, double *y) {
+  if (!M) {
+    for (int i = threadIdx.x; i < r; i += blockDim.x) y[i] = x[i];
+    return;
+  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = wid; i < r; i += nw) {
     const double *mc = M + (size_t)r * i;
@@ -837,6 +857,10 @@ __device__ inline void mv_trans(const double *M, int r, const double *x, double 
 
 // y = M x: one thread per output, consecutive threads on consecutive rows
 __device__ inline void mv_plain(const double *M, int r, const double *x, double *y) {
+  if (!M) {
+    for (int i = threadIdx.x; i < r; i += blockDim.x) y[i] = x[i];
+    return;
+  }
   for (int i = threadIdx.x; i < r; i += blockDim.x) {
     double a = 0.0;
     for (int l = 0; l < r; ++l) a += M[i + (size_t)r * l] * x[l];
@@ -849,7 +873,7 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
                                                          int given, double *p1, double *w1,
                                                          double *t2, double *p2, double *w2,
                                                          double *p, double *ws, double *sc,
-                                                         double *g) {
+                                                         double *g, double *ge) {
   __shared__ double red[16];
   const int tid = threadIdx.x;
   mv_trans(M, r, t1, p1);
@@ -878,6 +902,7 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
   double b1 = 0.0, b2 = 0.0;
   for (int i = tid; i < r; i += blockDim.x) {
     ws[i] = w1[i] + w2[i];
+    if (ge) ge[i] = t2[i] - g[i];  // V0^T e with e = e1 - V0 w2
     b1 += w2[i] * t2[i];
     b2 += w2[i] * g[i];
   }
@@ -893,9 +918,9 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
 hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const double *t1,
                             const double *dd, int given, double *p1, double *w1, double *t2,
                             double *p2, double *w2, double *p, double *ws, double *sc,
-                            double *g, hipStream_t s) {
+                            double *g, double *ge, hipStream_t s) {
   hipLaunchKernelGGL(isvd_gram_kernel, dim3(1), dim3(1024), 0, s, M, G0, r, t1, dd, given, p1,
-                     w1, t2, p2, w2, p, ws, sc, g);
+                     w1, t2, p2, w2, p, ws, sc, g, ge);
   return hipGetLastError();
 }
 
@@ -932,6 +957,35 @@ __global__ void scale_kernel(double *x, int64_t n, double a) {
 hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, a);
+  return hipGetLastError();
+}
+
+// C (m x n, ld ldc) = op(A) B with op(A) = A (m x k, ld lda) or A^T (A k x m),
+// B k x n (ld ldb); one thread per output (small r x r products).
+__global__ void small_gemm_kernel(int transA, const double *A, int64_t lda, const double *B,
+                                  int64_t ldb, double *C, int64_t ldc, int m, int n, int k) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int i = idx % m, j = idx / m;
+  const double *bc = B + ldb * j;
+  double acc = 0.0;
+  if (transA) {
+    const double *ac = A + lda * i;
+#pragma unroll 8
+    for (int l = 0; l < k; ++l) acc += ac[l] * bc[l];
+  } else {
+#pragma unroll 8
+    for (int l = 0; l < k; ++l) acc += A[i + lda * l] * bc[l];
+  }
+  C[i + ldc * j] = acc;
+}
+
+hipError_t launch_small_gemm(int transA, const double *A, int64_t lda, const double *B,
+                             int64_t ldb, double *C, int64_t ldc, int m, int n, int k,
+                             hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s,
+                     transA, A, lda, B, ldb, C, ldc, m, n, k);
   return hipGetLastError();
 }
 

@@ -79,10 +79,15 @@ hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, cons
 int gemv_t_blocks(int64_t R);
 hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, double *part,
                          int nb, hipStream_t s);
+hipError_t launch_gemv_t_mapped(const double *V, int64_t ldv, const RowMap &map, int64_t R, int r,
+                                const double *x, double *part, int nb, hipStream_t s);
+hipError_t launch_small_gemm(int transA, const double *A, int64_t lda, const double *B,
+                             int64_t ldb, double *C, int64_t ldc, int m, int n, int k,
+                             hipStream_t s);
 hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const double *t1,
                             const double *dd, int given, double *p1, double *w1, double *t2,
                             double *p2, double *w2, double *p, double *ws, double *sc,
-                            double *g, hipStream_t s);
+                            double *g, double *ge, hipStream_t s);
 hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
                             double inv_q, int grow, double *Gn, hipStream_t s);
 hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s);
