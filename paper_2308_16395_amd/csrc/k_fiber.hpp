@@ -256,9 +256,14 @@ __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int 
 }
 
 // Projection P = X x W^T (and, with RESID, the residual and norm partials).
+// With `stage` (output stride ao == 1, i.e. the outputs of one fibre are
+// contiguous and consecutive fibres adjacent), each wave writes its tile
+// through LDS so that the stores are contiguous instead of one cache line per
+// lane.
 template <int MT, int NT, bool CONTIG, bool RESID, int PREC, class TIN, class TOUT>
 __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, int m0, int mcount,
-                                                         FiberOut out, double *partials) {
+                                                         FiberOut out, double *partials,
+                                                         int stage) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int64_t mbeg = (int64_t)m0 + (int64_t)blockIdx.y * (16 * MT);
@@ -277,18 +282,40 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
   double x2 = 0.0, e2 = 0.0;
   project_wave<MT, NT, CONTIG, PREC, RESID, TIN>(in, w, mbeg, mend, base, acc, x2);
 
+  if (stage) {
+    extern __shared__ double stage_raw[];
+    constexpr int TW = 16 * MT;  // outputs per fibre in this block
+    constexpr int TWP = TW + 1;  // padded LDS row (odd: spreads the banks)
+    TOUT *tile = reinterpret_cast<TOUT *>(stage_raw) + (size_t)wid * (16 * NT) * TWP;
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int64_t f = fib[nt];
-    if (f >= in.F) continue;
-    const int64_t fq = f / out.ao, fr = f - fq * out.ao;
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t m = mbeg + 16 * mt + acc_row<PREC>(grp, v);
-        if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (TOUT)acc[mt][nt][v];
-      }
+        for (int v = 0; v < 4; ++v)
+          tile[(16 * nt + col) * TWP + 16 * mt + acc_row<PREC>(grp, v)] = (TOUT)acc[mt][nt][v];
+    __syncthreads();
+    const int64_t mlen = (mend - mbeg) < TW ? (mend - mbeg) : TW;
+    const int64_t total = (int64_t)(16 * NT) * mlen;
+    for (int64_t idx = lane; idx < total; idx += 64) {
+      const int64_t fl = idx / mlen, ml = idx - fl * mlen;
+      const int64_t f = fwave + fl;
+      if (f < in.F) op[mbeg + ml + out.mo * f] = tile[fl * TWP + ml];
+    }
+  } else {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int64_t f = fib[nt];
+      if (f >= in.F) continue;
+      const int64_t fq = f / out.ao, fr = f - fq * out.ao;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = mbeg + 16 * mt + acc_row<PREC>(grp, v);
+          if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (TOUT)acc[mt][nt][v];
+        }
+    }
   }
 
   if constexpr (RESID) {
@@ -330,8 +357,12 @@ hipError_t launch_fiber_t(const FiberIn &in, const FiberW &w, int m0, int mcount
   const int64_t per_block = 64 * NT;
   dim3 grid((unsigned)((in.F + per_block - 1) / per_block),
             RESID ? 1u : (unsigned)((mcount + 16 * MT - 1) / (16 * MT)));
+  // stage the output tile through LDS when the output stride is 1 and the
+  // tile fits (4 waves x 16 NT fibres x 16 MT outputs)
+  const size_t lds = (size_t)4 * 16 * NT * (16 * MT + 1) * sizeof(TOUT);
+  const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
   hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT>), grid,
-                     dim3(kThreads), 0, s, in, w, m0, mcount, out, partials);
+                     dim3(kThreads), stage ? lds : 0, s, in, w, m0, mcount, out, partials, stage);
   return hipGetLastError();
 }
 

@@ -201,12 +201,14 @@ hipError_t launch_rot_typed(const FiberIn &in, const T *w, int64_t ldw, int m0, 
   ST_ROT_CASE(2, 2)
   ST_ROT_CASE(4, 2)
   ST_ROT_CASE(6, 2)
-  ST_ROT_CASE(8, 1)
-  ST_ROT_CASE(9, 1)
-  ST_ROT_CASE(10, 1)
-  ST_ROT_CASE(11, 1)
+  // the FP64 rotation reuses each staged W value for two fibre tiles
+  constexpr int NTW = std::is_same<T, double>::value ? 2 : 1;
+  ST_ROT_CASE(8, NTW)
+  ST_ROT_CASE(9, NTW)
+  ST_ROT_CASE(10, NTW)
+  ST_ROT_CASE(11, NTW)
 #undef ST_ROT_CASE
-  return launch_rot_t<12, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+  return launch_rot_t<12, NTW, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
 }
 
 }  // namespace
