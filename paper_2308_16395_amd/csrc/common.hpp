@@ -130,10 +130,12 @@ struct FiberW {
 };
 
 // Input/output element types: FP32 -> FP32, FP32 -> FP64 and FP64 -> FP64.
-int fiber_blocks(int64_t F);
+// resid_partials must hold 2 * fiber_max_blocks(in.F) doubles; `nparts`
+// (optional) receives the number of blocks that wrote a pair.
+int fiber_max_blocks(int64_t F);
 hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int mcount,
                                 const FiberOut &out, double *resid_partials, Prec prec,
-                                hipStream_t s);
+                                hipStream_t s, int *nparts = nullptr);
 
 // Mode-d rotation (MAPPED input) with FP64 products and sums:
 // P[f][m] = sum_k X'[f][k] W[m][k] (W row-major, ld ldw), X'[f][k] = X[f][k]
@@ -163,10 +165,13 @@ hipError_t launch_reduce_pairs(const double *partials, int count, double *out, h
 
 // Typed fibre launchers (one translation unit each).
 hipError_t launch_fiber_ff(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                           const FiberOut &out, double *partials, Prec prec, hipStream_t s);
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s,
+                           int *nparts);
 hipError_t launch_fiber_fd(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                           const FiberOut &out, double *partials, Prec prec, hipStream_t s);
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s,
+                           int *nparts);
 hipError_t launch_fiber_dd(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                           const FiberOut &out, double *partials, Prec prec, hipStream_t s);
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s,
+                           int *nparts);
 
 }  // namespace st

@@ -251,19 +251,14 @@ struct st_handle {
     return e;
   }
 
-  // Number of blocks launch_fiber_project uses for F fibres (norm partials).
-  static int fiber_nblocks(int64_t F) {
-    return (int)(F >= 256 * 128 ? (F + 127) / 128 : (F + 63) / 64);
-  }
-
   // Norms of E and X for mode k into hpin[0..1].
   int project_resid(const FiberIn &in, const FiberW &w, int rows, const FiberOut &out, Prec pr,
                     int group) {
-    const int nb = fiber_nblocks(in.F);
-    hipError_t e = part.ensure(2 * (size_t)nb);
+    hipError_t e = part.ensure(2 * (size_t)fiber_max_blocks(in.F));
     if (e != hipSuccess) return hipfail(e, "partials");
+    int nb = 0;
     tic();
-    e = launch_fiber_project(in, w, 0, rows, out, part.p, pr, stream);
+    e = launch_fiber_project(in, w, 0, rows, out, part.p, pr, stream, &nb);
     if (e != hipSuccess) return hipfail(e, "fiber projection + residual");
     // P = D x_k U^T and E = D - P x_k U: 4 F n r flops; D read once, P written once
     toc(group, 4.0 * in.F * in.n * rows, 4.0 * in.F * (in.n + rows));
@@ -1420,13 +1415,13 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
     w.w_lo = bl;
     w.ldw_bf = ldb;
   }
-  const int nb = st_handle::fiber_nblocks(in.F);
+  int nb = 0;
   if (e == hipSuccess && norms) {
-    e = hipMalloc((void **)&part, 2 * (size_t)nb * sizeof(double));
+    e = hipMalloc((void **)&part, 2 * (size_t)fiber_max_blocks(in.F) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&sum, 2 * sizeof(double));
   }
   if (e == hipSuccess)
-    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, 0, lo, rows}, part, pr, s);
+    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, 0, lo, rows}, part, pr, s, &nb);
   if (e == hipSuccess && norms) e = launch_reduce_pairs(part, nb, sum, s);
   if (e == hipSuccess && norms)
     e = hipMemcpyAsync(norms, sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -326,6 +326,19 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (fib[nt] >= in.F) continue;
+        if constexpr (CONTIG && PREC != 2) {
+          // contiguous FP32 fibre: rows 16 jt + 4 grp .. + 3 in one 16-byte load
+          const int64_t j0 = 16 * jt + 4 * grp;
+          if (j0 + 4 <= in.n) {
+            const f32x4 xv = *reinterpret_cast<const f32x4 *>(xp + base[nt] + j0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double e = (double)xv[v] - (double)racc[nt][v];
+              e2 += e * e;
+            }
+            continue;
+          }
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t j = 16 * jt + acc_row<PREC>(grp, v);
@@ -351,9 +364,265 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused projection + residual with the fibres held in registers.
+//
+// Lane (col, grp) keeps, for each of its NT fibres, the elements
+// j = kidx(i, grp, v) = 16 i + 4 grp + v (16 i + grp + 4 v for the FP64 MFMA),
+// i < JT, v < 4: exactly the rows its residual accumulator holds after the
+// reconstruction MFMAs of tile i, and a valid K split for the projection MFMAs
+// (the four lane groups of one MFMA step cover four distinct k). Each fibre is
+// read from memory once; the projection, the residual and both norms run from
+// registers. Used when n <= 16 JT and all rows of W fit one block.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__device__ constexpr int kidx(int i, int grp, int v) {
+  return 16 * i + (PREC == 2 ? grp + 4 * v : 4 * grp + v);
+}
+
+template <int MT, int NT, int JT, int PREC, class TIN, class TOUT>
+__global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, int mcount,
+                                                         FiberOut out, double *partials,
+                                                         int stage) {
+  // element type kept in registers: the input's, or FP64 for the FP64 MFMA
+  using XT = typename std::conditional<PREC == 2 || std::is_same<TIN, double>::value, double,
+                                       float>::type;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int64_t n = in.n;
+  const int64_t fwave = ((int64_t)blockIdx.x * 4 + wid) * (16 * NT);
+  const TIN *xp = cptr<TIN>(in.x);
+  TOUT *op = reinterpret_cast<TOUT *>(out.p);
+
+  int64_t fib[NT], base[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    fib[nt] = fwave + 16 * nt + col;
+    base[nt] = fiber_base(in, fib[nt]);
+  }
+  XT x[NT][JT][4];
+  double x2 = 0.0;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int i = 0; i < JT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t k = kidx<PREC>(i, grp, v);
+        const XT val = (base[nt] >= 0 && k < n) ? (XT)xp[base[nt] + in.a * k] : (XT)0;
+        x[nt][i][v] = val;
+        x2 += (double)val * (double)val;
+      }
+
+  AccT<PREC> acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = AccT<PREC>{0, 0, 0, 0};
+  if constexpr (PREC == 1) {
+    // 16x16x32 bf16 steps over tile pairs (i0, i0 + 1): 8 K values per lane
+#pragma unroll
+    for (int i0 = 0; i0 < JT; i0 += 2) {
+      bf16x8 xh[NT], xl[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        float t[8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          t[v] = (float)x[nt][i0][v];
+          t[4 + v] = (i0 + 1 < JT) ? (float)x[nt][i0 + 1 < JT ? i0 + 1 : i0][v] : 0.0f;
+        }
+        split8(t, xh[nt], xl[nt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int m = 16 * mt + col;
+        float t[8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t k0 = kidx<PREC>(i0, grp, v), k1 = kidx<PREC>(i0 + 1, grp, v);
+          t[v] = (m < mcount && k0 < n) ? w.w[m * w.ldw + k0] : 0.0f;
+          t[4 + v] = (i0 + 1 < JT && m < mcount && k1 < n) ? w.w[m * w.ldw + k1] : 0.0f;
+        }
+        bf16x8 wh, wl;
+        split8(t, wh, wl);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          acc[mt][nt] = mfma_bf(wh, xh[nt], acc[mt][nt]);
+          acc[mt][nt] = mfma_bf(wh, xl[nt], acc[mt][nt]);
+          acc[mt][nt] = mfma_bf(wl, xh[nt], acc[mt][nt]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < JT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t k = kidx<PREC>(i, grp, v);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int m = 16 * mt + col;
+          const bool ok = m < mcount && k < n;
+          if constexpr (PREC == 2) {
+            const double a = ok ? w.w64[m * w.ldw + k] : 0.0;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              acc[mt][nt] = mfma_f64(a, (double)x[nt][i][v], acc[mt][nt]);
+          } else {
+            const float a = ok ? w.w[m * w.ldw + k] : 0.0f;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              acc[mt][nt] = mfma4(a, (float)x[nt][i][v], acc[mt][nt]);
+          }
+        }
+      }
+  }
+
+  // P = D x_k W^T (this block holds all rows of W)
+  const int64_t mend = mcount;
+  if (stage) {
+    extern __shared__ double stage_raw[];
+    constexpr int TW = 16 * MT;
+    constexpr int TWP = TW + 1;
+    TOUT *tile = reinterpret_cast<TOUT *>(stage_raw) + (size_t)wid * (16 * NT) * TWP;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          tile[(16 * nt + col) * TWP + 16 * mt + acc_row<PREC>(grp, v)] = (TOUT)acc[mt][nt][v];
+    __syncthreads();
+    const int64_t total = (int64_t)(16 * NT) * mend;
+    for (int64_t idx = lane; idx < total; idx += 64) {
+      const int64_t fl = idx / mend, ml = idx - fl * mend;
+      const int64_t f = fwave + fl;
+      if (f < in.F) op[ml + out.mo * f] = tile[fl * TWP + ml];
+    }
+  } else {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int64_t f = fib[nt];
+      if (f >= in.F) continue;
+      const int64_t fq = f / out.ao, fr = f - fq * out.ao;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = 16 * mt + acc_row<PREC>(grp, v);
+          if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (TOUT)acc[mt][nt][v];
+        }
+    }
+  }
+
+  // E = D - P x_k W: reconstruction tile i holds rows kidx(i, grp, v) per lane
+  double e2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < JT; ++i) {
+    AccT<PREC> racc[NT];
+    recon_tile<MT, NT, PREC>(w, mcount, n, i, acc, racc);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (fib[nt] >= in.F) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (kidx<PREC>(i, grp, v) < n) {
+          const double e = (double)x[nt][i][v] - (double)racc[nt][v];
+          e2 += e * e;
+        }
+      }
+    }
+  }
+  __shared__ double red[2][4];
+  e2 = wave_sum(e2);
+  x2 = wave_sum(x2);
+  if (lane == 0) {
+    red[0][wid] = e2;
+    red[1][wid] = x2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x + 0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    partials[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+template <int MT, int JT, int PREC, class TIN, class TOUT>
+hipError_t launch_resid_t(const FiberIn &in, const FiberW &w, int mcount, const FiberOut &out,
+                          double *partials, hipStream_t s, int *np) {
+  // two fibre tiles per wave when the registers allow it and there are enough
+  // fibres to fill the chip
+  constexpr bool wide = !(PREC == 2 || std::is_same<TIN, double>::value) && JT * MT <= 24;
+  if (wide && in.F >= 256 * 128) {
+    constexpr int NT = wide ? 2 : 1;
+    const size_t lds = (size_t)4 * 16 * NT * (16 * MT + 1) * sizeof(TOUT);
+    const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
+    dim3 grid((unsigned)((in.F + 64 * NT - 1) / (64 * NT)));
+    hipLaunchKernelGGL((resid_kernel<MT, NT, JT, PREC, TIN, TOUT>), grid, dim3(kThreads),
+                       stage ? lds : 0, s, in, w, mcount, out, partials, stage);
+    if (np) *np = (int)grid.x;
+  } else {
+    const size_t lds = (size_t)4 * 16 * (16 * MT + 1) * sizeof(TOUT);
+    const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
+    dim3 grid((unsigned)((in.F + 63) / 64));
+    hipLaunchKernelGGL((resid_kernel<MT, 1, JT, PREC, TIN, TOUT>), grid, dim3(kThreads),
+                       stage ? lds : 0, s, in, w, mcount, out, partials, stage);
+    if (np) *np = (int)grid.x;
+  }
+  return hipGetLastError();
+}
+
+template <int MT, int JT, class TIN, class TOUT>
+hipError_t launch_resid_p(const FiberIn &in, const FiberW &w, int mcount, const FiberOut &out,
+                          double *partials, Prec prec, hipStream_t s, int *np) {
+  if (prec == Prec::BF16X3)
+    return launch_resid_t<MT, JT, 1, TIN, TOUT>(in, w, mcount, out, partials, s, np);
+  if (prec == Prec::FP64)
+    return launch_resid_t<MT, JT, 2, TIN, TOUT>(in, w, mcount, out, partials, s, np);
+  return launch_resid_t<MT, JT, 0, TIN, TOUT>(in, w, mcount, out, partials, s, np);
+}
+
+template <int MT, class TIN, class TOUT>
+hipError_t launch_resid_j(const FiberIn &in, const FiberW &w, int mcount, const FiberOut &out,
+                          double *partials, Prec prec, hipStream_t s, int *np) {
+  const int64_t jt = (in.n + 15) / 16;
+  if (jt <= 1) return launch_resid_p<MT, 1, TIN, TOUT>(in, w, mcount, out, partials, prec, s, np);
+  if (jt <= 2) return launch_resid_p<MT, 2, TIN, TOUT>(in, w, mcount, out, partials, prec, s, np);
+  if (jt <= 4) return launch_resid_p<MT, 4, TIN, TOUT>(in, w, mcount, out, partials, prec, s, np);
+  return launch_resid_p<MT, 8, TIN, TOUT>(in, w, mcount, out, partials, prec, s, np);
+}
+
+// The register-resident residual kernel, when it applies (returns false if not).
+template <class TIN, class TOUT>
+bool try_launch_resid(const FiberIn &in, const FiberW &w, int m0, int mcount, const FiberOut &out,
+                      double *partials, Prec prec, hipStream_t s, hipError_t &err, int *np) {
+  // used for the FP64 partial cores (modes 2..d-1); for FP32 input the
+  // streaming kernel with vector loads runs at higher occupancy
+  if constexpr (!std::is_same<TIN, double>::value) {
+    return false;
+  } else {
+    if (partials == nullptr || in.mapped || m0 != 0 || in.n > 128 || mcount > 128) return false;
+    const int tiles = (mcount + 15) / 16;
+#define ST_RESID_CASE(T_)                                                                \
+    if (tiles <= T_) {                                                                   \
+      err = launch_resid_j<T_, TIN, TOUT>(in, w, mcount, out, partials, prec, s, np);    \
+      return true;                                                                       \
+    }
+    ST_RESID_CASE(1)
+    ST_RESID_CASE(2)
+    ST_RESID_CASE(3)
+    ST_RESID_CASE(4)
+    ST_RESID_CASE(6)
+    ST_RESID_CASE(8)
+#undef ST_RESID_CASE
+    return false;
+  }
+}
+
 template <int MT, int NT, bool CONTIG, bool RESID, int PREC, class TIN, class TOUT>
 hipError_t launch_fiber_t(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                          const FiberOut &out, double *partials, hipStream_t s) {
+                          const FiberOut &out, double *partials, hipStream_t s, int *nparts) {
   const int64_t per_block = 64 * NT;
   dim3 grid((unsigned)((in.F + per_block - 1) / per_block),
             RESID ? 1u : (unsigned)((mcount + 16 * MT - 1) / (16 * MT)));
@@ -363,45 +632,50 @@ hipError_t launch_fiber_t(const FiberIn &in, const FiberW &w, int m0, int mcount
   const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
   hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT>), grid,
                      dim3(kThreads), stage ? lds : 0, s, in, w, m0, mcount, out, partials, stage);
+  if (nparts) *nparts = (int)grid.x;
   return hipGetLastError();
 }
 
 template <int MT, int NT, bool CONTIG, bool RESID, class TIN, class TOUT>
 hipError_t launch_fiber_p(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                          const FiberOut &out, double *partials, Prec prec, hipStream_t s) {
+                          const FiberOut &out, double *partials, Prec prec, hipStream_t s,
+                          int *np) {
   if (prec == Prec::BF16X3)
-    return launch_fiber_t<MT, NT, CONTIG, RESID, 1, TIN, TOUT>(in, w, m0, mcount, out, partials, s);
+    return launch_fiber_t<MT, NT, CONTIG, RESID, 1, TIN, TOUT>(in, w, m0, mcount, out, partials, s,
+                                                               np);
   if (prec == Prec::FP64)
-    return launch_fiber_t<MT, NT, CONTIG, RESID, 2, TIN, TOUT>(in, w, m0, mcount, out, partials, s);
-  return launch_fiber_t<MT, NT, CONTIG, RESID, 0, TIN, TOUT>(in, w, m0, mcount, out, partials, s);
+    return launch_fiber_t<MT, NT, CONTIG, RESID, 2, TIN, TOUT>(in, w, m0, mcount, out, partials, s,
+                                                               np);
+  return launch_fiber_t<MT, NT, CONTIG, RESID, 0, TIN, TOUT>(in, w, m0, mcount, out, partials, s,
+                                                             np);
 }
 
 template <int MT, int NT, class TIN, class TOUT>
 hipError_t launch_fiber_c(const FiberIn &in, const FiberW &w, int m0, int mcount,
                           const FiberOut &out, double *partials, bool contig, Prec prec,
-                          hipStream_t s) {
+                          hipStream_t s, int *np) {
   const bool resid = partials != nullptr;
   if constexpr (std::is_same<TIN, float>::value) {
     if (contig) {
       if (resid)
-        return launch_fiber_p<MT, NT, true, true, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s);
-      return launch_fiber_p<MT, NT, true, false, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s);
+        return launch_fiber_p<MT, NT, true, true, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s, np);
+      return launch_fiber_p<MT, NT, true, false, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s, np);
     }
   }
   if (resid)
-    return launch_fiber_p<MT, NT, false, true, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s);
-  return launch_fiber_p<MT, NT, false, false, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s);
+    return launch_fiber_p<MT, NT, false, true, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s, np);
+  return launch_fiber_p<MT, NT, false, false, TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s, np);
 }
 
 template <int NT, class TIN, class TOUT>
 hipError_t launch_fiber_n(const FiberIn &in, const FiberW &w, int m0, int mcount,
                           const FiberOut &out, double *partials, bool contig, Prec prec,
-                          hipStream_t s) {
+                          hipStream_t s, int *np) {
   // smallest instantiated tile count >= the rows needed (padding wastes MFMA work)
   const int tiles = (mcount + 15) / 16;
 #define ST_FIBER_CASE(T)                                                                        \
   if (tiles <= T)                                                                               \
-    return launch_fiber_c<T, NT, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s);
+    return launch_fiber_c<T, NT, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s, np);
   ST_FIBER_CASE(1)
   ST_FIBER_CASE(2)
   ST_FIBER_CASE(3)
@@ -411,7 +685,7 @@ hipError_t launch_fiber_n(const FiberIn &in, const FiberW &w, int m0, int mcount
   ST_FIBER_CASE(12)
 #undef ST_FIBER_CASE
   if (tiles <= 16 || partials == nullptr)
-    return launch_fiber_c<16, NT, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s);
+    return launch_fiber_c<16, NT, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s, np);
   return hipErrorInvalidValue;  // fused residual needs all rows in one block
 }
 
@@ -420,15 +694,22 @@ inline bool contiguous(const FiberIn &in) {
          (reinterpret_cast<uintptr_t>(in.x) & 15) == 0;
 }
 
+// nparts (optional) receives the number of blocks that wrote residual partials;
+// it never exceeds fiber_max_blocks(in.F).
 template <class TIN, class TOUT>
 hipError_t launch_fiber_typed(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                              const FiberOut &out, double *partials, Prec prec, hipStream_t s) {
+                              const FiberOut &out, double *partials, Prec prec, hipStream_t s,
+                              int *nparts) {
+  if (nparts) *nparts = 0;
   if (in.F <= 0 || mcount <= 0) return hipSuccess;
+  hipError_t rerr = hipSuccess;
+  if (try_launch_resid<TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s, rerr, nparts))
+    return rerr;
   const bool contig = contiguous(in);
   // two fibre tiles per wave when there are enough fibres to fill the chip
   if (in.F >= 256 * 128)
-    return launch_fiber_n<2, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s);
-  return launch_fiber_n<1, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s);
+    return launch_fiber_n<2, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s, nparts);
+  return launch_fiber_n<1, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s, nparts);
 }
 
 }  // namespace fk

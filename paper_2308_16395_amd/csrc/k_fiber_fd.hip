@@ -5,8 +5,9 @@
 namespace st {
 
 hipError_t launch_fiber_fd(const FiberIn &in, const FiberW &w, int m0, int mcount,
-                           const FiberOut &out, double *partials, Prec prec, hipStream_t s) {
-  return fk::launch_fiber_typed<float, double>(in, w, m0, mcount, out, partials, prec, s);
+                           const FiberOut &out, double *partials, Prec prec, hipStream_t s,
+                           int *nparts) {
+  return fk::launch_fiber_typed<float, double>(in, w, m0, mcount, out, partials, prec, s, nparts);
 }
 
 }  // namespace st

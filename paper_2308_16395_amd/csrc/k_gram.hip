@@ -245,19 +245,24 @@ hipError_t launch_gram_typed(const FiberIn &in, const FiberW &w, int rows, doubl
 
 }  // namespace
 
-int fiber_blocks(int64_t F) { return (int)(F >= 256 * 128 ? (F + 127) / 128 : (F + 63) / 64); }
+// one 64-fibre block per 64 fibres at most (launches with two fibre tiles per
+// wave use half as many)
+int fiber_max_blocks(int64_t F) { return (int)((F + 63) / 64); }
 
 hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int mcount,
                                 const FiberOut &out, double *resid_partials, Prec prec,
-                                hipStream_t s) {
+                                hipStream_t s, int *nparts) {
   if (in.mapped && resid_partials != nullptr) return hipErrorInvalidValue;
   if (prec == Prec::FP64 && w.w64 == nullptr) return hipErrorInvalidValue;
   if (prec == Prec::BF16X3 && (w.w_hi == nullptr || w.w_lo == nullptr))
     return hipErrorInvalidValue;
   if (prec == Prec::FP32 && w.w == nullptr) return hipErrorInvalidValue;
-  if (!in.x64 && !out.o64) return launch_fiber_ff(in, w, m0, mcount, out, resid_partials, prec, s);
-  if (!in.x64 && out.o64) return launch_fiber_fd(in, w, m0, mcount, out, resid_partials, prec, s);
-  if (in.x64 && out.o64) return launch_fiber_dd(in, w, m0, mcount, out, resid_partials, prec, s);
+  if (!in.x64 && !out.o64)
+    return launch_fiber_ff(in, w, m0, mcount, out, resid_partials, prec, s, nparts);
+  if (!in.x64 && out.o64)
+    return launch_fiber_fd(in, w, m0, mcount, out, resid_partials, prec, s, nparts);
+  if (in.x64 && out.o64)
+    return launch_fiber_dd(in, w, m0, mcount, out, resid_partials, prec, s, nparts);
   return hipErrorInvalidValue;  // FP64 -> FP32 is not a path of the update
 }
 
