@@ -201,7 +201,7 @@ int st_reconstruct_slice(const st_handle *h, int64_t t, float *out);
  * projection X x_mode U^T). out is the column-major device tensor with
  * dims[mode] replaced by rows. If norms (host, 2 doubles) is not NULL it
  * receives ||X - (X x_mode A) x_mode A^T||_F^2 and ||X||_F^2 in FP64, the
- * residual and norm of Alg. 4 (rows <= 256 then). precision: enum
+ * residual and norm of Alg. 4 (rows <= 384 then). precision: enum
  * st_precision. stream: hipStream_t or NULL for the null stream; the call
  * returns after the work has finished. Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
 int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,

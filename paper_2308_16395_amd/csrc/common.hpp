@@ -148,15 +148,18 @@ hipError_t launch_rot64(const FiberIn &in, const void *w, int w64, int64_t ldw, 
                         hipStream_t s);
 
 // Gram of the residual E = X - (X x W^T) x W (or of X itself when rows == 0)
-// over all fibres: writes per-block partials of the lower-triangular 16x16
-// tiles; `gram_reduce` sums them in FP64 into G (n x n, column-major). The
+// over all fibres, summed in FP64 in a fixed order into G (n x n,
+// column-major; when G is null only the per-block partials of the
+// lower-triangular 16x16 tiles are written, for launch_gram_reduce). The
 // residual is formed with FP64 products when `e64` (W.w64 must be set), else
-// with FP32 products; the Gram products use `gp` (FP64: E kept in FP64).
+// with FP32 products; the Gram products use `gp` (FP64: E kept in FP64; when E
+// of all n rows does not fit LDS, the Gram is formed over pairs of 128-row
+// chunks and G must be given). `partials` holds gram_partial_elems doubles.
 enum class GramPrec : int { FP32 = 0, BF16X3 = 1, FP64 = 2 };
-int gram_blocks(int64_t F);
-size_t gram_partial_elems(int64_t n, int nblocks);
+int gram_blocks(int64_t F, int64_t n, GramPrec gp);
+size_t gram_partial_elems(int64_t n, int nblocks, GramPrec gp);
 hipError_t launch_gram(const FiberIn &in, const FiberW &w, int rows, double *partials,
-                       int nblocks, GramPrec gp, bool e64, hipStream_t s);
+                       int nblocks, GramPrec gp, bool e64, hipStream_t s, double *G);
 hipError_t launch_gram_reduce(const double *partials, int nblocks, int64_t n, double *G,
                               hipStream_t s);
 

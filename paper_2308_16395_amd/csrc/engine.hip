@@ -276,8 +276,8 @@ struct st_handle {
   // hpin[0..nk), eigenvectors in G.
   int gram_eig(const FiberIn &in, const FiberW &w, int rows, int64_t nk, GramPrec pr,
                bool e64) {
-    const int gnb = gram_blocks(in.F);
-    hipError_t e = gram_part.ensure(gram_partial_elems(nk, gnb));
+    const int gnb = gram_blocks(in.F, nk, pr);
+    hipError_t e = gram_part.ensure(gram_partial_elems(nk, gnb, pr));
     if (e == hipSuccess) e = G.ensure((size_t)nk * nk);
     if (e == hipSuccess) e = eigval.ensure(nk);
     if (e == hipSuccess) e = eigwork.ensure(nk);
@@ -285,12 +285,11 @@ struct st_handle {
     if (e == hipSuccess) e = ensure_pinned(nk + 8);
     if (e != hipSuccess) return hipfail(e, "gram buffers");
     tic();
-    e = launch_gram(in, w, rows, gram_part.p, gnb, pr, e64, stream);
+    e = launch_gram(in, w, rows, gram_part.p, gnb, pr, e64, stream, G.p);
     if (e != hipSuccess) return hipfail(e, "gram");
     // recompute E (4 F n r) and form the lower triangle of E E^T (F n^2)
-    toc(ST_K_GRAM, 4.0 * in.F * nk * rows + 1.0 * in.F * nk * nk, 4.0 * in.F * nk);
-    e = launch_gram_reduce(gram_part.p, gnb, nk, G.p, stream);
-    if (e != hipSuccess) return hipfail(e, "gram reduce");
+    toc(ST_K_GRAM, 4.0 * in.F * nk * rows + 1.0 * in.F * nk * nk,
+        (in.x64 ? 8.0 : 4.0) * in.F * nk);
     tic();
     rocblas_status rs = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_lower,
                                          (rocblas_int)nk, G.p, (rocblas_int)nk, eigval.p,
@@ -443,8 +442,11 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
         rc = hipfail(e, "init partial core");
         break;
       }
+      // the initial chain runs once: exact FP64 products in every form (with
+      // FP32 products, V = A^T U_d S^-1 would carry u s_1 / s_k in its columns
+      // of small singular value and start out non-orthonormal)
       FiberOut out{T[sel].p, 1, a, rk};
-      e = launch_fiber_project(in, wmat(k), 0, (int)rk, out, nullptr, prec, stream);
+      e = launch_fiber_project(in, wmat(k), 0, (int)rk, out, nullptr, Prec::FP64, stream);
       if (e != hipSuccess) {
         rc = hipfail(e, "init projection");
         break;
@@ -1383,7 +1385,7 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
     if (k < mode) lo *= dims[k];
     if (k > mode) hi *= dims[k];
   }
-  if (norms && rows > 256) return ST_EINVAL;
+  if (norms && rows > 384) return ST_EINVAL;
   const int64_t nk = dims[mode];
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
@@ -1447,7 +1449,7 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
     if (k > mode) hi *= dims[k];
   }
   const int64_t nk = dims[mode];
-  if (nk > (gram_precision == 2 ? 256 : 512) || rows > nk) return ST_EINVAL;
+  if (nk > 512 || rows > nk) return ST_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;  // initialises the runtime
@@ -1459,20 +1461,19 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
   FiberW w{};
   w.w = a;
   w.ldw = nk;
-  const int nb = gram_blocks(in.F);
+  const GramPrec gp = (GramPrec)gram_precision;
+  const int nb = gram_blocks(in.F, nk, gp);
   double *part = nullptr, *G = nullptr, *a64 = nullptr;
   // the FP64 Gram also forms the residual with FP64 products
   const bool e64 = gram_precision == 2 && rows > 0;
-  hipError_t e = hipMalloc((void **)&part, gram_partial_elems(nk, nb) * sizeof(double));
+  hipError_t e = hipMalloc((void **)&part, gram_partial_elems(nk, nb, gp) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void **)&G, nk * nk * sizeof(double));
   if (e == hipSuccess && e64) {
     e = hipMalloc((void **)&a64, rows * nk * sizeof(double));
     if (e == hipSuccess) e = launch_f32_to_f64(a, rows * nk, a64, s);
     w.w64 = a64;
   }
-  if (e == hipSuccess)
-    e = launch_gram(in, w, (int)rows, part, nb, (GramPrec)gram_precision, e64, s);
-  if (e == hipSuccess) e = launch_gram_reduce(part, nb, nk, G, s);
+  if (e == hipSuccess) e = launch_gram(in, w, (int)rows, part, nb, gp, e64, s, G);
   if (e == hipSuccess) e = hipMemcpyAsync(g, G, nk * nk * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (part) (void)hipFree(part);

@@ -706,6 +706,26 @@ hipError_t launch_fiber_typed(const FiberIn &in, const FiberW &w, int m0, int mc
   if (try_launch_resid<TIN, TOUT>(in, w, m0, mcount, out, partials, prec, s, rerr, nparts))
     return rerr;
   const bool contig = contiguous(in);
+  const int tiles = (mcount + 15) / 16;
+  if (partials != nullptr && tiles > 16) {
+    // fused residual with more than 256 rows: all of them in one block, one
+    // fibre tile per wave
+    if (tiles > 24) return hipErrorInvalidValue;
+    if constexpr (std::is_same<TIN, float>::value) {
+      if (contig) {
+        if (tiles <= 20)
+          return launch_fiber_p<20, 1, true, true, TIN, TOUT>(in, w, m0, mcount, out, partials,
+                                                              prec, s, nparts);
+        return launch_fiber_p<24, 1, true, true, TIN, TOUT>(in, w, m0, mcount, out, partials,
+                                                            prec, s, nparts);
+      }
+    }
+    if (tiles <= 20)
+      return launch_fiber_p<20, 1, false, true, TIN, TOUT>(in, w, m0, mcount, out, partials, prec,
+                                                           s, nparts);
+    return launch_fiber_p<24, 1, false, true, TIN, TOUT>(in, w, m0, mcount, out, partials, prec,
+                                                         s, nparts);
+  }
   // two fibre tiles per wave when there are enough fibres to fill the chip
   if (in.F >= 256 * 128)
     return launch_fiber_n<2, TIN, TOUT>(in, w, m0, mcount, out, partials, contig, prec, s, nparts);

@@ -6,6 +6,8 @@
 // fibres (all n rows) into LDS, then the waves accumulate their share of the
 // lower-triangular 16x16 tiles of G = sum_f e_f e_f^T. Per-block partials are
 // summed in a fixed order, so G is deterministic.
+#include <algorithm>
+
 #include "k_fiber.hpp"
 
 namespace st {
@@ -156,6 +158,129 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(FiberIn in, FiberW w, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 Gram for fibres too long to hold E in LDS: rows are split into chunks
+// of kChunk and the Gram is formed one chunk pair (I >= J) at a time, with E of
+// both chunks in LDS (the projection is recomputed per fibre tile and pass).
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 128;        // rows per chunk (8 tiles)
+constexpr int kChunkT = kChunk / 16;
+
+template <int MT, bool CONTIG, int PE, class TIN>
+__global__ __launch_bounds__(kThreads) void gram_pair_kernel(FiberIn in, FiberW w, int rows,
+                                                             int64_t i0, int64_t j0,
+                                                             double *partials) {
+  constexpr int LDE = lde<2>();
+  extern __shared__ double es2[];
+  double *esI = es2;                    // [kChunk][LDE]
+  double *esJ = es2 + kChunk * LDE;     // [kChunk][LDE] (unused when i0 == j0)
+  const bool same = i0 == j0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int64_t n = in.n;
+  const TIN *xp = cptr<TIN>(in.x);
+  const int ntl = same ? kChunkT * (kChunkT + 1) / 2 : kChunkT * kChunkT;
+  f64x4 gacc[16];
+  int tI[16], tJ[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    gacc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int t = wid + 4 * q;
+    if (t < ntl) {
+      if (same) {
+        tile_ij(t, tI[q], tJ[q]);
+      } else {
+        tI[q] = t / kChunkT;
+        tJ[q] = t % kChunkT;
+      }
+    } else {
+      tI[q] = -1;
+      tJ[q] = -1;
+    }
+  }
+  const int64_t ftiles = (in.F + 63) / 64;
+  for (int64_t it = blockIdx.x; it < ftiles; it += gridDim.x) {
+    const int64_t fw = it * 64 + wid * 16;
+    const int64_t base[1] = {fiber_base(in, fw + col)};
+    if (rows > 0) {
+      AccT<PE> acc[MT][1];
+      double dummy = 0.0;
+      project_wave<MT, 1, CONTIG, PE, false, TIN>(in, w, 0, rows, base, acc, dummy);
+      for (int h = 0; h < (same ? 1 : 2); ++h) {
+        const int64_t c0 = h == 0 ? i0 : j0;
+        double *es = h == 0 ? esI : esJ;
+        for (int lt = 0; lt < kChunkT; ++lt) {
+          const int jt = (int)(c0 / 16) + lt;
+          AccT<PE> racc[1];
+          recon_tile<MT, 1, PE>(w, rows, n, jt, acc, racc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t j = 16 * (int64_t)jt + acc_row<PE>(grp, v);
+            const double x = (base[0] >= 0 && j < n) ? (double)xp[base[0] + in.a * j] : 0.0;
+            es[(j - c0) * LDE + wid * 16 + col] = (j < n) ? x - (double)racc[0][v] : 0.0;
+          }
+        }
+      }
+    } else {
+      for (int h = 0; h < (same ? 1 : 2); ++h) {
+        const int64_t c0 = h == 0 ? i0 : j0;
+        double *es = h == 0 ? esI : esJ;
+        for (int lt = 0; lt < kChunkT; ++lt) {
+          double xv[4];
+          load_x4<CONTIG, TIN>(in, base[0], c0 + 16 * lt + 4 * grp, xv);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) es[(16 * lt + 4 * grp + v) * LDE + wid * 16 + col] = xv[v];
+        }
+      }
+    }
+    __syncthreads();
+    const double *eJ = same ? esI : esJ;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (tI[q] < 0) continue;
+      const double *ra = esI + (16 * tI[q] + col) * LDE;
+      const double *rb = eJ + (16 * tJ[q] + col) * LDE;
+#pragma unroll
+      for (int kb = 0; kb < 64; kb += 32)
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          gacc[q] = mfma_f64(ra[kb + 8 * grp + s], rb[kb + 8 * grp + s], gacc[q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (tI[q] < 0) continue;
+    const int t = wid + 4 * q;
+    double *dst = partials + ((size_t)blockIdx.x * ntl + t) * 256;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[acc_row<2>(grp, v) * 16 + col] = gacc[q][v];
+  }
+}
+
+__global__ void gram_pair_reduce_kernel(const double *partials, int nblocks, int64_t i0,
+                                        int64_t j0, int64_t n, double *G) {
+  const bool same = i0 == j0;
+  const int ntl = same ? kChunkT * (kChunkT + 1) / 2 : kChunkT * kChunkT;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ntl * 256) return;
+  const int t = (int)(idx / 256), e = (int)(idx % 256);
+  int ti, tj;
+  if (same) {
+    tile_ij(t, ti, tj);
+  } else {
+    ti = t / kChunkT;
+    tj = t % kChunkT;
+  }
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partials[((size_t)b * ntl + t) * 256 + e];
+  const int64_t i = i0 + 16 * ti + e / 16, j = j0 + 16 * tj + e % 16;
+  if (i < n && j < n) {
+    G[i + n * j] = s;
+    G[j + n * i] = s;
+  }
+}
+
 __global__ void gram_reduce_kernel(const double *partials, int nblocks, int ntiles, int64_t n,
                                    double *G) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,6 +368,61 @@ hipError_t launch_gram_typed(const FiberIn &in, const FiberW &w, int rows, doubl
   return hipErrorInvalidValue;
 }
 
+template <int MT, bool CONTIG, int PE, class TIN>
+hipError_t launch_gram_pairs_k(const FiberIn &in, const FiberW &w, int rows, double *partials,
+                               int nblocks, double *G, hipStream_t s) {
+  const size_t lds = (size_t)2 * kChunk * lde<2>() * sizeof(double);
+  const void *fn = (const void *)gram_pair_kernel<MT, CONTIG, PE, TIN>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t nch = (in.n + kChunk - 1) / kChunk;
+  for (int64_t I = 0; I < nch; ++I)
+    for (int64_t J = 0; J <= I; ++J) {
+      hipLaunchKernelGGL((gram_pair_kernel<MT, CONTIG, PE, TIN>), dim3((unsigned)nblocks),
+                         dim3(kThreads), lds, s, in, w, rows, I * kChunk, J * kChunk, partials);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const int ntl = (I == J) ? kChunkT * (kChunkT + 1) / 2 : kChunkT * kChunkT;
+      hipLaunchKernelGGL(gram_pair_reduce_kernel, dim3((unsigned)((ntl * 256 + 255) / 256)),
+                         dim3(256), 0, s, partials, nblocks, I * kChunk, J * kChunk, in.n, G);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+template <int MT, class TIN>
+hipError_t launch_gram_pairs_t(const FiberIn &in, const FiberW &w, int rows, double *partials,
+                               int nblocks, bool contig, bool e64, double *G, hipStream_t s) {
+  if constexpr (std::is_same<TIN, float>::value) {
+    if (contig) {
+      if (e64) return launch_gram_pairs_k<MT, true, 2, TIN>(in, w, rows, partials, nblocks, G, s);
+      return launch_gram_pairs_k<MT, true, 0, TIN>(in, w, rows, partials, nblocks, G, s);
+    }
+  }
+  if (e64) return launch_gram_pairs_k<MT, false, 2, TIN>(in, w, rows, partials, nblocks, G, s);
+  return launch_gram_pairs_k<MT, false, 0, TIN>(in, w, rows, partials, nblocks, G, s);
+}
+
+template <class TIN>
+hipError_t launch_gram_pairs_typed(const FiberIn &in, const FiberW &w, int rows,
+                                   double *partials, int nblocks, bool e64, double *G,
+                                   hipStream_t s) {
+  const bool contig = contiguous(in);
+  const int tiles = (rows + 15) / 16;
+  if (tiles <= 1)
+    return launch_gram_pairs_t<1, TIN>(in, w, rows, partials, nblocks, contig, e64, G, s);
+  if (tiles <= 2)
+    return launch_gram_pairs_t<2, TIN>(in, w, rows, partials, nblocks, contig, e64, G, s);
+  if (tiles <= 4)
+    return launch_gram_pairs_t<4, TIN>(in, w, rows, partials, nblocks, contig, e64, G, s);
+  if (tiles <= 8)
+    return launch_gram_pairs_t<8, TIN>(in, w, rows, partials, nblocks, contig, e64, G, s);
+  if (tiles <= 16)
+    return launch_gram_pairs_t<16, TIN>(in, w, rows, partials, nblocks, contig, e64, G, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 // one 64-fibre block per 64 fibres at most (launches with two fibre tiles per
@@ -266,24 +446,43 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
   return hipErrorInvalidValue;  // FP64 -> FP32 is not a path of the update
 }
 
-int gram_blocks(int64_t F) {
-  const int64_t t = (F + 63) / 64;
-  return (int)(t < 512 ? t : 512);
+static bool gram_uses_pairs(int64_t n, GramPrec gp) {
+  return gp == GramPrec::FP64 && gram_lds(n, 2) > 160 * 1024;
 }
 
-size_t gram_partial_elems(int64_t n, int nblocks) {
+static int64_t gram_tiles(int64_t n, GramPrec gp) {
+  if (gram_uses_pairs(n, gp)) return kChunkT * kChunkT;  // per chunk pair
   const int64_t jt = (n + 15) / 16;
-  return (size_t)nblocks * (size_t)(jt * (jt + 1) / 2) * 256;
+  return jt * (jt + 1) / 2;
+}
+
+int gram_blocks(int64_t F, int64_t n, GramPrec gp) {
+  // at most 512 blocks, and partials of at most 64 MB
+  const int64_t t = (F + 63) / 64;
+  const int64_t by_mem = std::max<int64_t>(16, (64ll << 20) / (gram_tiles(n, gp) * 256 * 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>({t, (int64_t)512, by_mem}));
+}
+
+size_t gram_partial_elems(int64_t n, int nblocks, GramPrec gp) {
+  return (size_t)nblocks * (size_t)gram_tiles(n, gp) * 256;
 }
 
 hipError_t launch_gram(const FiberIn &in, const FiberW &w, int rows, double *partials,
-                       int nblocks, GramPrec gp, bool e64, hipStream_t s) {
+                       int nblocks, GramPrec gp, bool e64, hipStream_t s, double *G) {
   if (in.F <= 0) return hipSuccess;
   const int g = (int)gp;
-  if (gram_lds(in.n, g) > 160 * 1024) return hipErrorInvalidValue;  // E tile must fit in LDS
   if (rows > 0 && (e64 ? w.w64 == nullptr : w.w == nullptr)) return hipErrorInvalidValue;
-  if (in.x64) return launch_gram_typed<double>(in, w, rows, partials, nblocks, g, e64, s);
-  return launch_gram_typed<float>(in, w, rows, partials, nblocks, g, e64, s);
+  if (gram_uses_pairs(in.n, gp)) {
+    // E of two row chunks at a time in FP64; G is written directly
+    if (G == nullptr) return hipErrorInvalidValue;
+    if (in.x64) return launch_gram_pairs_typed<double>(in, w, rows, partials, nblocks, e64, G, s);
+    return launch_gram_pairs_typed<float>(in, w, rows, partials, nblocks, e64, G, s);
+  }
+  if (gram_lds(in.n, g) > 160 * 1024) return hipErrorInvalidValue;  // E tile must fit in LDS
+  hipError_t e = in.x64 ? launch_gram_typed<double>(in, w, rows, partials, nblocks, g, e64, s)
+                        : launch_gram_typed<float>(in, w, rows, partials, nblocks, g, e64, s);
+  if (e == hipSuccess && G != nullptr) e = launch_gram_reduce(partials, nblocks, in.n, G, s);
+  return e;
 }
 
 hipError_t launch_gram_reduce(const double *partials, int nblocks, int64_t n, double *G,

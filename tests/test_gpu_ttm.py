@@ -35,6 +35,8 @@ CASES = [
     ((64, 48, 5), 1, 48),
     ((200, 30), 0, 130),
     ((12, 300), 1, 260),
+    ((320, 6, 2), 0, 300),   # fused residual with more than 256 rows (20 tiles)
+    ((24, 380), 1, 370),     # 24 tiles
 ]
 
 
@@ -50,7 +52,7 @@ def test_ttm_projection_and_residual(dims, mode, rows, precision, rtol):
     # column-major device layout: the C-ordered array of the reversed axes
     xd = torch.from_numpy(np.ascontiguousarray(x.ravel(order="F"))).cuda()
     a = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()  # rows x n, row-major
-    want_norms = rows <= 256
+    want_norms = rows <= 384
     res = ttm(xd, dims, mode, a, precision=precision, norms=want_norms)
     out, norms = (res if want_norms else (res, None))
     y_ref, e2_ref, x2_ref = _ref(x, u.T, mode)
@@ -78,6 +80,9 @@ GRAM_CASES = [
     ((24, 17, 5), 1, 6),
     ((9, 20), 1, 0),
     ((260, 7), 0, 40),
+    ((400, 6), 0, 0),        # FP64: E too long for LDS, formed over row-chunk pairs
+    ((400, 6), 0, 24),
+    ((7, 512, 2), 1, 37),
 ]
 
 
@@ -91,13 +96,6 @@ def test_gram_against_numpy(dims, mode, rows, precision, rtol):
     x, u = _case(dims, mode, max(rows, 1), sum(dims) + 7 * rows)
     xd = torch.from_numpy(np.ascontiguousarray(x.ravel(order="F"))).cuda()
     a = torch.from_numpy(np.ascontiguousarray(u.T)).cuda() if rows > 0 else None
-    if precision == "fp64" and dims[mode] > 256:
-        # the FP64 residual tile is held in LDS: longer fibres are rejected
-        from paper_2308_16395_amd.binding import StError
-
-        with pytest.raises(StError):
-            gram(xd, dims, mode, a, precision=precision)
-        return
     g = gram(xd, dims, mode, a, precision=precision)
     x64 = np.moveaxis(x.astype(np.float64), mode, 0).reshape(dims[mode], -1)
     if rows > 0:
@@ -114,3 +112,14 @@ def test_gram_against_numpy(dims, mode, rows, precision, rtol):
         # the residual is formed in FP32, so its Gram is accurate to ~1e-6 of ||X||^2
         tol = max(rtol * np.abs(ref).max(), 1e-5 * xx)
     np.testing.assert_allclose(g, ref, rtol=0, atol=tol)
+
+
+def test_gram_rejects_fibres_longer_than_512():
+    import torch
+
+    from paper_2308_16395_amd.binding import StError, gram
+
+    dims = (520, 3)
+    xd = torch.zeros(520 * 3, device="cuda")
+    with pytest.raises(StError):
+        gram(xd, dims, 0, None, precision="fp64")
