@@ -100,6 +100,49 @@ def ttm_chain_flops(shape, modes_to):
     return total
 
 
+def large_bench(n_init=20, warmup=3, steps=30):
+    """FP32 vs bf16x3 products on the 512 x 512 x 256 Fourier stream (tau 1e-4),
+    factored core form: updates per second and the mode-1 TTM roofline."""
+    import torch
+
+    import paper_2308_16395_amd as pkg
+    from synth import make_stream
+
+    s = make_stream(4)
+    dev = torch.device("cuda:0")
+    total = n_init + warmup + steps
+    data = torch.empty((total, math.prod(s.dims)), dtype=torch.float32, device=dev)
+    for t in range(total):
+        data[t] = s.slice_torch(t, dev, torch.float32)
+    torch.cuda.synchronize()
+    out = dict(workload="random-Fourier 512x512x256, tau 1e-4, init 20 slices, "
+                        f"{steps} timed updates after {warmup}, factored core form")
+    for prec in ("fp32", "bf16x3"):
+        st = pkg.StreamingTucker(s.dims, 1e-4, precision=prec, profile=True,
+                                 core_update="factored")
+        st.init(data[:n_init].reshape(-1), n_init)
+        for t in range(n_init, n_init + warmup):
+            st.update(data[t])
+        st.profile(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(n_init + warmup, total):
+            st.update(data[t])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = st.profile()
+        out[prec] = dict(value=round(steps / dt, 2), ranks=list(st.ranks),
+                         recon_error_bound=st.recon_error()[0],
+                         ttm_roofline=ttm_roofline(prof, prec),
+                         ttm_ms_per_step=round((prof["ttm1"]["ms"] + prof["ttm"]["ms"]) / steps,
+                                               4))
+        st.close()
+        log(f"large stream {prec}: {out[prec]}")
+    del data
+    torch.cuda.empty_cache()
+    return out
+
+
 def grad_bench(reps=5):
     """Reconstruct / Project forward and VJPs at GRAD_DIMS, FP32 products."""
     import numpy as np
@@ -183,6 +226,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the Reconstruct/Project forward and VJP timings")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the FP32 vs bf16x3 comparison on the 512x512x256 stream")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size "
                          "kernel against which HBM byte counters are calibrated)")
@@ -319,9 +364,12 @@ def main():
         log(f"timing the FP64 oracle on {k} updates")
         result["cpu_baseline"] = cpu_baseline(host, n_init, w["tau"], k)
         del host
+    del data
+    torch.cuda.empty_cache()
+    if not args.no_large:
+        log("FP32 vs bf16x3 on the 512x512x256 stream")
+        result["large_stream"] = large_bench()
     if not args.no_grad:
-        del data
-        torch.cuda.empty_cache()
         log("timing Reconstruct/Project forward and VJPs")
         result["differentiation"] = grad_bench()
     print(json.dumps(result), flush=True)

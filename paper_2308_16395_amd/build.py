@@ -37,9 +37,16 @@ def compile_flags():
     ]
 
 
+# Per-source code generation options. The rotations keep their MFMA
+# accumulators in VGPRs: with the default AGPR form the compiler copies the
+# loop-carried accumulators between the two register files on every K block.
+SOURCE_FLAGS = {"k_rot.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *compile_flags(), *SOURCE_FLAGS.get(src, []), "-c",
+           os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")

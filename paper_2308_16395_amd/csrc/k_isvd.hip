@@ -169,8 +169,9 @@ static hipError_t launch_isvd_tr(const IsvdArgs &a, int nblocks, hipStream_t s) 
 
 hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s) {
   if (a.r > 8 * 256 || pass < 1 || pass > 2) return hipErrorInvalidValue;
-  // 64-row tiles while they fit in LDS, else 32-row tiles
-  const bool tall = isvd_lds(a.r, 64) <= kIsvdMaxLds;
+  // 64-row tiles while two blocks fit a CU's LDS, else 32-row tiles (one block
+  // per CU leaves the tile load and the two compute phases unoverlapped)
+  const bool tall = 2 * isvd_lds(a.r, 64) <= kIsvdMaxLds;
   if (!tall && isvd_lds(a.r, 32) > kIsvdMaxLds) return hipErrorInvalidValue;
   if (pass == 1)
     return tall ? launch_isvd_tr<1, 64>(a, nblocks, s) : launch_isvd_tr<1, 32>(a, nblocks, s);
@@ -785,19 +786,33 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t l
     xx += xv[i] * xv[i];
     src[i] = row < R ? (MAPPED ? map_new_to_old(map, row) : row) : -1;
   }
-  for (int j = wid; j < r; j += 4) {
-    const double *col = V0 + ldv * (int64_t)j;
-    double s = 0.0;
-    if (full) {
+  // four columns per wave and iteration: 4 kGemvRPL loads in flight per lane
+  // before the reductions
+  constexpr int CPI = 4;
+  for (int j0 = wid * CPI; j0 < r; j0 += 4 * CPI) {
+    double s[CPI];
 #pragma unroll
-      for (int i = 0; i < kGemvRPL; ++i) s += col[row0 + 64 * i] * xv[i];
-    } else {
+    for (int c = 0; c < CPI; ++c) {
+      // columns past r repeat column j0 and are not stored
+      const int j = (j0 + c < r) ? j0 + c : j0;
+      const double *col = V0 + ldv * (int64_t)j;
+      s[c] = 0.0;
+      if (full) {
 #pragma unroll
-      for (int i = 0; i < kGemvRPL; ++i)
-        if (src[i] >= 0) s += col[src[i]] * xv[i];
+        for (int i = 0; i < kGemvRPL; ++i) s[c] += col[row0 + 64 * i] * xv[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < kGemvRPL; ++i) {
+          const double v = col[src[i] >= 0 ? src[i] : 0];
+          s[c] += (src[i] >= 0 ? v : 0.0) * xv[i];
+        }
+      }
     }
-    s = wave_sum(s);
-    if (lane == 0) part[(size_t)j * nb + blockIdx.x] = s;
+#pragma unroll
+    for (int c = 0; c < CPI; ++c) {
+      const double t = wave_sum(s[c]);
+      if (lane == 0 && j0 + c < r) part[(size_t)(j0 + c) * nb + blockIdx.x] = t;
+    }
   }
   if (wid == 0) {
     xx = wave_sum(xx);

@@ -19,11 +19,13 @@ using namespace fk;
 // e[f] = extra[f] - sum_k X[f][k] p[k] formed in FP64 from the row itself
 // (the ISVD complement e = d - V p, never stored).
 // W (type T, row-major) is staged through LDS one 32-wide K block at a time and
-// shared by the block's four waves; each wave owns NT x 16 rows.
+// shared by the block's four waves; each wave owns NT x 16 rows. The register
+// budget is that of two waves per SIMD (256 VGPRs, accumulators included: the
+// library builds this file with the MFMA operands in VGPRs), so one wave's
+// LDS and global latency is covered by the other's MFMAs.
 template <int MT, int NT, int EXTRA, class T>
-__global__ __launch_bounds__(kThreads) void rot_kernel(FiberIn in, const T *w, int64_t ldw,
-                                                       int m0, int mcount, FiberOut out,
-                                                       const double *pvec) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void rot_kernel(
+    FiberIn in, const T *w, int64_t ldw, int m0, int mcount, FiberOut out, const double *pvec) {
   constexpr int LDW = std::is_same<T, double>::value ? 33 : 36;  // LDS row stride of W
   __shared__ T ws[MT * 16 * LDW];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -50,70 +52,106 @@ __global__ __launch_bounds__(kThreads) void rot_kernel(FiberIn in, const T *w, i
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) dot[nt] = 0.0;
 
-  // Software pipeline: the W slice and the X values of K block kb + 32 are
-  // loaded into registers while the MFMAs consume block kb (W from LDS).
+  // The X values of K block kb + 32 (the HBM stream) are loaded into registers
+  // while the MFMAs consume block kb; the W slice (small, L2-resident) is
+  // staged into LDS at the top of each block. All loads are unconditional:
+  // rows of W past mend are clamped (they only feed output rows that are not
+  // stored), out-of-range K and X elements read a valid element and are
+  // replaced by zero, so the loads of a block issue back to back. The mask
+  // xok (bit 8 nt + s: element in range) is applied when the block is
+  // consumed, so that the prefetch stays in flight.
   constexpr int WPT = MT * 16 * 32 / kThreads;  // W elements staged per thread
-  T wreg[WPT];
-  double xreg[NT][8];
-  auto load_w = [&](int64_t kb) {
-#pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-      const int idx = threadIdx.x + kThreads * q;
-      const int r = idx >> 5, c = idx & 31;
-      const int64_t m = mbeg + r, k = kb + c;
-      wreg[q] = (m < mend && k < K) ? w[m * ldw + k] : (T)0;
-    }
-  };
+  T xreg[NT][8];
+  uint32_t xok = 0;
   auto load_x = [&](int64_t kb) {
+    xok = 0;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int64_t k = kb + 4 * s + grp;
-        xreg[nt][s] = (k < n && base[nt] >= 0) ? (double)xp[base[nt] + in.a * k] : 0.0;
+        const bool ok = k < n && base[nt] >= 0;
+        xreg[nt][s] = xp[ok ? base[nt] + in.a * k : 0];
+        xok |= (ok ? 1u : 0u) << (8 * nt + s);
       }
   };
-  // FP64 state: prefetch one block ahead. The FP32 core keeps the loads in
-  // the iteration (its lower register use allows two waves per SIMD instead).
-  constexpr bool kPipe = std::is_same<T, double>::value;
-  if constexpr (kPipe) {
-    load_w(0);
-    load_x(0);
-  }
-  for (int64_t kb = 0; kb < K; kb += 32) {
-    __syncthreads();  // the previous block's LDS reads are done
-    if constexpr (!kPipe) {
-      load_w(kb);
-      load_x(kb);
-    }
+  const int wc = threadIdx.x & 31, wr0 = threadIdx.x >> 5;
+  // stage K block kb: W into LDS, X (and the ISVD dot) into xd; start the
+  // prefetch of the next block
+  auto stage = [&](int64_t kb, double (&xd)[NT][8]) {
+    T wv[WPT];
+    const bool kok = kb + wc < K;
+    const int64_t kk = kok ? kb + wc : 0;
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
-      const int idx = threadIdx.x + kThreads * q;
-      ws[(idx >> 5) * LDW + (idx & 31)] = wreg[q];
+      const int64_t m = mbeg + wr0 + 8 * q;
+      wv[q] = w[(m < mend ? m : mend - 1) * ldw + kk];
     }
-    double xd[NT][8];
+    double pv[8];
+    if (EXTRA == 2) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int64_t k = kb + 4 * s + grp;
+        pv[s] = pvec[k < n ? k : n - 1];  // multiplies a zero X element when k >= n
+      }
+    }
+    __syncthreads();  // the previous block's LDS reads are done
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) ws[(wr0 + 8 * q) * LDW + wc] = kok ? wv[q] : (T)0;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int s = 0; s < 8; ++s) xd[nt][s] = xreg[nt][s];
-    __syncthreads();
-    if constexpr (kPipe) {
-      if (kb + 32 < K) {
-        load_w(kb + 32);
-        load_x(kb + 32);
-      }
-    }
+      for (int s = 0; s < 8; ++s)
+        xd[nt][s] = ((xok >> (8 * nt + s)) & 1u) ? (double)xreg[nt][s] : 0.0;
     if (EXTRA == 2) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int64_t k = kb + 4 * s + grp;
-          if (k < n) dot[nt] += xd[nt][s] * pvec[k];
-        }
+        for (int s = 0; s < 8; ++s) dot[nt] += xd[nt][s] * pv[s];
     }
-    if (EXTRA && kb + 32 > n) {  // the block holding element n
-      const int sl = (int)(n - kb);
+    __syncthreads();
+    if (kb + 32 < K) load_x(kb + 32);
+  };
+  // MFMA s covers k = kb + 4 s .. kb + 4 s + 3 (lane group grp holds
+  // k = kb + 4 s + grp); the MT column tiles of one step are independent. The
+  // W values of step s + 1 are read from LDS while the MFMAs of step s run;
+  // the scheduling barrier keeps the compiler from hoisting the reads of all
+  // steps at once (which would cost 2 MT registers per step).
+  const T *wl = ws + col * LDW + grp;
+  auto steps = [&](int count, const double (&xd)[NT][8]) {
+    T wa[2][MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) wa[0][mt] = wl[16 * mt * LDW];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (s < count) {
+        if (s + 1 < 8 && s + 1 < count) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) wa[(s + 1) & 1][mt] = wl[16 * mt * LDW + 4 * (s + 1)];
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = mfma_f64((double)wa[s & 1][mt], xd[nt][s], acc[mt][nt]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  };
+  // full blocks below kmain hold no extra element; the last block [kmain, K)
+  // holds element n when there is one
+  const int64_t kmain = EXTRA ? (n / 32) * 32 : (K / 32) * 32;
+  load_x(0);
+  for (int64_t kb = 0; kb < kmain; kb += 32) {
+    double xd[NT][8];
+    stage(kb, xd);
+    steps(8, xd);
+  }
+  if (kmain < K) {
+    double xd[NT][8];
+    stage(kmain, xd);
+    if (EXTRA) {
+      const int sl = (int)(n - kmain);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         double ev = 0.0;
@@ -133,21 +171,8 @@ __global__ __launch_bounds__(kThreads) void rot_kernel(FiberIn in, const T *w, i
         }
       }
     }
-    // MFMA s covers k = kb + 4 s .. kb + 4 s + 3 (lane group grp holds k = kb + 4 s + grp);
-    // steps wholly past K (the tail of the last block) are skipped
-    const int steps = (int)((K - kb + 3) / 4 < 8 ? (K - kb + 3) / 4 : 8);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const T *wr = ws + (16 * mt + col) * LDW + grp;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        if (s < steps) {
-          const double a = (double)wr[4 * s];
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a, xd[nt][s], acc[mt][nt]);
-        }
-      }
-    }
+    // steps wholly past K are skipped
+    steps((int)((K - kmain + 3) >> 2), xd);
   }
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
@@ -198,17 +223,18 @@ hipError_t launch_rot_typed(const FiberIn &in, const T *w, int64_t ldw, int m0, 
   const int tiles = (mcount + 15) / 16;
 #define ST_ROT_CASE(T_, NT_) \
   if (tiles <= T_) return launch_rot_t<T_, NT_, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+  // narrow outputs reuse each staged W value for two fibre tiles; wide ones
+  // keep one fibre tile per wave so that the accumulators fit two waves per SIMD
+  constexpr int NT6 = std::is_same<T, double>::value ? 1 : 2;
   ST_ROT_CASE(2, 2)
   ST_ROT_CASE(4, 2)
-  ST_ROT_CASE(6, 2)
-  // the FP64 rotation reuses each staged W value for two fibre tiles
-  constexpr int NTW = std::is_same<T, double>::value ? 2 : 1;
-  ST_ROT_CASE(8, NTW)
-  ST_ROT_CASE(9, NTW)
-  ST_ROT_CASE(10, NTW)
-  ST_ROT_CASE(11, NTW)
+  ST_ROT_CASE(6, NT6)
+  ST_ROT_CASE(8, 1)
+  ST_ROT_CASE(9, 1)
+  ST_ROT_CASE(10, 1)
+  ST_ROT_CASE(11, 1)
 #undef ST_ROT_CASE
-  return launch_rot_t<12, NTW, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+  return launch_rot_t<12, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
 }
 
 }  // namespace
