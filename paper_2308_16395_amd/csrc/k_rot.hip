@@ -23,6 +23,10 @@ using namespace fk;
 // budget is that of two waves per SIMD (256 VGPRs, accumulators included: the
 // library builds this file with the MFMA operands in VGPRs), so one wave's
 // LDS and global latency is covered by the other's MFMAs.
+// W prefetch for the FP32 core up to 11 column tiles (fits the budget below)
+template <class T, int MT>
+constexpr bool kRotPrefetchW = std::is_same<T, float>::value && MT <= 11;
+
 template <int MT, int NT, int EXTRA, class T>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void rot_kernel(
     FiberIn in, const T *w, int64_t ldw, int m0, int mcount, FiberOut out, const double *pvec) {
@@ -76,17 +80,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       }
   };
   const int wc = threadIdx.x & 31, wr0 = threadIdx.x >> 5;
-  // stage K block kb: W into LDS, X (and the ISVD dot) into xd; start the
-  // prefetch of the next block
-  auto stage = [&](int64_t kb, double (&xd)[NT][8]) {
-    T wv[WPT];
-    const bool kok = kb + wc < K;
-    const int64_t kk = kok ? kb + wc : 0;
+  // Where the registers allow (PW), the W slice of the next block is fetched
+  // with the X prefetch; otherwise it is loaded at the top of its own block.
+  constexpr bool PW = kRotPrefetchW<T, MT>;
+  T wv[WPT];
+  auto load_w = [&](int64_t kb) {
+    const int64_t kk = (kb + wc < K) ? kb + wc : 0;
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
       const int64_t m = mbeg + wr0 + 8 * q;
       wv[q] = w[(m < mend ? m : mend - 1) * ldw + kk];
     }
+  };
+  // stage K block kb: W into LDS, X (and the ISVD dot) into xd; start the
+  // prefetch of the next block
+  auto stage = [&](int64_t kb, double (&xd)[NT][8]) {
+    if (!PW) load_w(kb);
+    const bool kok = kb + wc < K;
     double pv[8];
     if (EXTRA == 2) {
 #pragma unroll
@@ -110,7 +120,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int s = 0; s < 8; ++s) dot[nt] += xd[nt][s] * pv[s];
     }
     __syncthreads();
-    if (kb + 32 < K) load_x(kb + 32);
+    if (kb + 32 < K) {
+      load_x(kb + 32);
+      if (PW) load_w(kb + 32);
+    }
   };
   // MFMA s covers k = kb + 4 s .. kb + 4 s + 3 (lane group grp holds
   // k = kb + 4 s + grp); the MT column tiles of one step are independent. The
@@ -142,6 +155,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   // holds element n when there is one
   const int64_t kmain = EXTRA ? (n / 32) * 32 : (K / 32) * 32;
   load_x(0);
+  if (PW) load_w(0);
   for (int64_t kb = 0; kb < kmain; kb += 32) {
     double xd[NT][8];
     stage(kb, xd);
