@@ -62,6 +62,15 @@ __device__ inline const T *cptr(const void *p) {
   return reinterpret_cast<const T *>(p);
 }
 
+// p[idx] when ok, else 0, without a branch: the load itself is unconditional
+// (it reads p[0] when !ok), so a run of such loads issues back to back instead
+// of each waiting behind its own branch.
+template <class T>
+__device__ inline T load_or0(const T *p, int64_t idx, bool ok) {
+  const T v = p[ok ? idx : 0];
+  return ok ? v : (T)0;
+}
+
 // Base offset of fibre f (or -1 for an absent / padded fibre).
 __device__ inline int64_t fiber_base(const FiberIn &in, int64_t f) {
   if (f >= in.F) return -1;
@@ -85,7 +94,7 @@ __device__ inline void load_x8(const FiberIn &in, int64_t base, int64_t k0, OT (
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int64_t k = k0 + s;
-    x[s] = (base >= 0 && k < in.n) ? (OT)xp[base + in.a * k] : (OT)0;
+    x[s] = (OT)load_or0(xp, base + in.a * k, base >= 0 && k < in.n);
   }
 }
 
@@ -102,7 +111,7 @@ __device__ inline void load_w8(const FiberW &w, int64_t m, int64_t mend, int64_t
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int64_t k = k0 + s;
-    x[s] = (m < mend && k < K) ? w.w[m * w.ldw + k] : 0.0f;
+    x[s] = load_or0(w.w, m * w.ldw + k, m < mend && k < K);
   }
 }
 
@@ -111,7 +120,7 @@ __device__ inline void load_w8_f64(const double *w, int64_t ldw, int64_t m, int6
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int64_t k = k0 + s;
-    x[s] = (m < mend && k < K) ? w[m * ldw + k] : 0.0;
+    x[s] = load_or0(w, m * ldw + k, m < mend && k < K);
   }
 }
 
@@ -124,7 +133,7 @@ __device__ inline void load_wbf8(const __bf16 *wb, int64_t ld, int64_t m, int64_
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int64_t k = k0 + s;
-    x[s] = (m < mend && k < K) ? wb[m * ld + k] : (__bf16)0.0f;
+    x[s] = load_or0(wb, m * ld + k, m < mend && k < K);
   }
 }
 
@@ -210,7 +219,7 @@ __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t m = 16 * mt + grp + 4 * v;
-        const double a = (m < rows && j < n) ? w.w64[m * w.ldw + j] : 0.0;
+        const double a = load_or0(w.w64, m * w.ldw + j, m < rows && j < n);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) racc[nt] = mfma_f64(a, acc[mt][nt][v], racc[nt]);
       }
@@ -220,7 +229,7 @@ __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t m = 16 * mt + 4 * grp + v;
-        const float a = (m < rows && j < n) ? w.w[m * w.ldw + j] : 0.0f;
+        const float a = load_or0(w.w, m * w.ldw + j, m < rows && j < n);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) racc[nt] = mfma4(a, acc[mt][nt][v], racc[nt]);
       }
@@ -234,8 +243,8 @@ __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int 
         const int mt = 2 * q + s / 4;
         const int64_t m = 16 * mt + 4 * grp + (s & 3);
         const bool ok = mt < MT && m < rows && j < n;
-        ah[s] = ok ? w.w_hi[m * w.ldw_bf + j] : (__bf16)0.0f;
-        al[s] = ok ? w.w_lo[m * w.ldw_bf + j] : (__bf16)0.0f;
+        ah[s] = load_or0(w.w_hi, m * w.ldw_bf + j, ok);
+        al[s] = load_or0(w.w_lo, m * w.ldw_bf + j, ok);
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t k = kidx<PREC>(i, grp, v);
-        const XT val = (base[nt] >= 0 && k < n) ? (XT)xp[base[nt] + in.a * k] : (XT)0;
+        const XT val = (XT)load_or0(xp, base[nt] + in.a * k, base[nt] >= 0 && k < n);
         x[nt][i][v] = val;
         x2 += (double)val * (double)val;
       }
@@ -441,8 +450,8 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t k0 = kidx<PREC>(i0, grp, v), k1 = kidx<PREC>(i0 + 1, grp, v);
-          t[v] = (m < mcount && k0 < n) ? w.w[m * w.ldw + k0] : 0.0f;
-          t[4 + v] = (i0 + 1 < JT && m < mcount && k1 < n) ? w.w[m * w.ldw + k1] : 0.0f;
+          t[v] = load_or0(w.w, m * w.ldw + k0, m < mcount && k0 < n);
+          t[4 + v] = load_or0(w.w, m * w.ldw + k1, i0 + 1 < JT && m < mcount && k1 < n);
         }
         bf16x8 wh, wl;
         split8(t, wh, wl);
@@ -465,12 +474,12 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
           const int m = 16 * mt + col;
           const bool ok = m < mcount && k < n;
           if constexpr (PREC == 2) {
-            const double a = ok ? w.w64[m * w.ldw + k] : 0.0;
+            const double a = load_or0(w.w64, m * w.ldw + k, ok);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
               acc[mt][nt] = mfma_f64(a, (double)x[nt][i][v], acc[mt][nt]);
           } else {
-            const float a = ok ? w.w[m * w.ldw + k] : 0.0f;
+            const float a = load_or0(w.w, m * w.ldw + k, ok);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
               acc[mt][nt] = mfma4(a, (float)x[nt][i][v], acc[mt][nt]);

@@ -49,7 +49,7 @@ __device__ inline void load_x4(const FiberIn &in, int64_t base, int64_t j0, doub
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t j = j0 + v;
-    x[v] = (base >= 0 && j < in.n) ? (double)xp[base + in.a * j] : 0.0;
+    x[v] = (double)load_or0(xp, base + in.a * j, base >= 0 && j < in.n);
   }
 }
 
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(FiberIn in, FiberW w, in
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t j = 16 * jt + acc_row<PE>(grp, v);
-          const double x = (base[0] >= 0 && j < n) ? (double)xp[base[0] + in.a * j] : 0.0;
+          const double x = (double)load_or0(xp, base[0] + in.a * j, base[0] >= 0 && j < n);
           es[j * LDE + wid * 16 + col] = (ET)(x - (double)racc[0][v]);
         }
       }
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void gram_pair_kernel(FiberIn in, FiberW 
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int64_t j = 16 * (int64_t)jt + acc_row<PE>(grp, v);
-            const double x = (base[0] >= 0 && j < n) ? (double)xp[base[0] + in.a * j] : 0.0;
+            const double x = (double)load_or0(xp, base[0] + in.a * j, base[0] >= 0 && j < n);
             es[(j - c0) * LDE + wid * 16 + col] = (j < n) ? x - (double)racc[0][v] : 0.0;
           }
         }
