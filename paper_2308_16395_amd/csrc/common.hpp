@@ -54,6 +54,22 @@ __device__ inline double block_sum(double v, double *scratch) {
   return t;
 }
 
+// q = f / a, r = f % a for f, a >= 0, with 32-bit division when both fit (a
+// 64-bit division is a long instruction sequence on the GPU).
+__device__ inline void divmod_index(int64_t f, int64_t a, int64_t &q, int64_t &r) {
+  if (a == 1) {
+    q = f;
+    r = 0;
+  } else if (((uint64_t)f | (uint64_t)a) <= 0xffffffffull) {
+    const uint32_t qq = (uint32_t)f / (uint32_t)a;
+    q = qq;
+    r = f - (int64_t)qq * a;
+  } else {
+    q = f / a;
+    r = f - q * a;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Mapping of a column-major multi-index between two rank tuples.
 //
@@ -70,6 +86,19 @@ struct RowMap {
 
 __host__ __device__ inline int64_t map_new_to_old(const RowMap &m, int64_t row) {
   if (m.identity) return row;
+  if ((uint64_t)row <= 0xffffffffull) {
+    // 32-bit divisions (a 64-bit division is a long instruction sequence on the GPU)
+    uint32_t rr = (uint32_t)row, old = 0, stride = 1;
+    for (int k = 0; k < m.nm; ++k) {
+      const uint32_t rn = (uint32_t)m.r_new[k];
+      const uint32_t q = rr / rn, ik = rr - q * rn;
+      rr = q;
+      if (ik >= (uint32_t)m.r_old[k]) return -1;
+      old += ik * stride;
+      stride *= (uint32_t)m.r_old[k];
+    }
+    return (int64_t)old;
+  }
   int64_t old = 0, stride = 1;
   for (int k = 0; k < m.nm; ++k) {
     const int64_t rn = m.r_new[k];

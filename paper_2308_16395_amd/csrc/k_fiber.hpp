@@ -71,11 +71,30 @@ __device__ inline T load_or0(const T *p, int64_t idx, bool ok) {
   return ok ? v : (T)0;
 }
 
+// Row and column of flat index idx in a tile of rows of length len (idx < 2^24,
+// len >= 1): a float reciprocal and one correction instead of an integer
+// division (idx / len is exact to within one after the float product).
+__device__ inline void tile_rc(int idx, int len, float inv_len, int &row, int &colm) {
+  int q = (int)((float)idx * inv_len);
+  int r = idx - q * len;
+  if (r < 0) {
+    --q;
+    r += len;
+  } else if (r >= len) {
+    ++q;
+    r -= len;
+  }
+  row = q;
+  colm = r;
+}
+
 // Base offset of fibre f (or -1 for an absent / padded fibre).
 __device__ inline int64_t fiber_base(const FiberIn &in, int64_t f) {
   if (f >= in.F) return -1;
   if (in.mapped) return map_new_to_old(in.map, f);
-  return (f % in.a) + in.a * in.n * (f / in.a);
+  int64_t q, r;
+  divmod_index(f, in.a, q, r);
+  return r + in.a * in.n * q;
 }
 
 // Eight consecutive K values k0 .. k0 + 7 of one fibre, as operand type OT.
@@ -151,16 +170,51 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = AccT<PREC>{0, 0, 0, 0};
 
+  // The X values of K block kb + 32 are loaded while the MFMAs of block kb run.
+  // Loads are unconditional; xm (bit 8 nt + s: element in range) zeroes the
+  // out-of-range ones when the block is consumed, so the loads stay in flight.
+  const TIN *xp = cptr<TIN>(in.x);
+  TIN xr[NT][8];
+  uint32_t xm = 0;
+  auto fetch = [&](int64_t kb) {
+    const int64_t k0 = kb + 8 * grp;
+    xm = 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if constexpr (CONTIG && std::is_same<TIN, float>::value) {
+        if (base[nt] >= 0 && k0 + 8 <= in.n) {
+          const f32x4 *p = reinterpret_cast<const f32x4 *>(xp + base[nt] + k0);
+          const f32x4 u = p[0], v = p[1];
+          xr[nt][0] = u[0]; xr[nt][1] = u[1]; xr[nt][2] = u[2]; xr[nt][3] = u[3];
+          xr[nt][4] = v[0]; xr[nt][5] = v[1]; xr[nt][6] = v[2]; xr[nt][7] = v[3];
+          xm |= 0xffu << (8 * nt);
+          continue;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int64_t k = k0 + s;
+        const bool ok = base[nt] >= 0 && k < in.n;
+        xr[nt][s] = xp[ok ? base[nt] + in.a * k : 0];
+        xm |= (ok ? 1u : 0u) << (8 * nt + s);
+      }
+    }
+  };
+  fetch(0);
   for (int64_t kb = 0; kb < K; kb += 32) {
     const int64_t k0 = kb + 8 * grp;
     OpT<PREC> xv[NT][8];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      load_x8<CONTIG, TIN>(in, base[nt], k0, xv[nt]);
-      if (NORMX) {
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        xv[nt][s] = ((xm >> (8 * nt + s)) & 1u) ? (OpT<PREC>)xr[nt][s] : (OpT<PREC>)0;
+    if (kb + 32 < K) fetch(kb + 32);
+    if (NORMX) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
         for (int s = 0; s < 8; ++s) x2 += (double)xv[nt][s] * (double)xv[nt][s];
-      }
     }
     if constexpr (PREC == 0) {
 #pragma unroll
@@ -264,15 +318,68 @@ __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int 
   }
 }
 
+// Copy rows [mbeg, min(mend, mbeg + 16 MT)) of W (all n columns, in the form
+// the product precision reads) into LDS with row stride wld and point wv at
+// the copy (rows then count from mbeg). Ends with a block barrier.
+template <int MT, int PREC>
+__device__ inline void stage_w(const FiberW &w, int64_t mbeg, int64_t mend, int64_t n, int wld,
+                               double *lds, FiberW &wv) {
+  const int rows = (int)((mend - mbeg) < 16 * MT ? (mend - mbeg) : 16 * MT);
+  const int nn = (int)n, total = rows * nn;
+  if constexpr (PREC == 0) {
+    float *d = reinterpret_cast<float *>(lds);
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+      const int r = idx / nn, k = idx - r * nn;
+      d[r * wld + k] = w.w[(mbeg + r) * w.ldw + k];
+    }
+    wv.w = d;
+    wv.ldw = wld;
+  } else if constexpr (PREC == 2) {
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+      const int r = idx / nn, k = idx - r * nn;
+      lds[r * wld + k] = w.w64[(mbeg + r) * w.ldw + k];
+    }
+    wv.w64 = lds;
+    wv.ldw = wld;
+  } else {
+    __bf16 *h = reinterpret_cast<__bf16 *>(lds), *l = h + 16 * MT * wld;
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+      const int r = idx / nn, k = idx - r * nn;
+      h[r * wld + k] = w.w_hi[(mbeg + r) * w.ldw_bf + k];
+      l[r * wld + k] = w.w_lo[(mbeg + r) * w.ldw_bf + k];
+    }
+    wv.w_hi = h;
+    wv.w_lo = l;
+    wv.ldw_bf = wld;
+  }
+  __syncthreads();
+}
+
+// LDS row stride of the W copy: a multiple of 4 (FP32 / FP64: 16-byte vector
+// reads of FP32 rows) or 8 (bf16x8 reads), padded so that consecutive rows
+// start in different banks.
+template <int PREC>
+inline int w_lds_stride(int64_t n) {
+  return PREC == 1 ? (int)(((n + 7) / 8) * 8 + 8) : (int)(((n + 7) / 8) * 8 + 4);
+}
+template <int MT, int PREC>
+inline size_t w_lds_bytes(int wld) {
+  // bf16x3 keeps the hi and lo halves (2 x 2 bytes per element)
+  return (size_t)16 * MT * wld * (PREC == 2 ? 8 : 4);
+}
+
 // Projection P = X x W^T (and, with RESID, the residual and norm partials).
 // With `stage` (output stride ao == 1, i.e. the outputs of one fibre are
 // contiguous and consecutive fibres adjacent), each wave writes its tile
 // through LDS so that the stores are contiguous instead of one cache line per
-// lane.
-template <int MT, int NT, bool CONTIG, bool RESID, int PREC, class TIN, class TOUT>
+// lane. With WL the block's rows of W are first copied into LDS (row stride
+// wld) and both products read them from there; the output tile then reuses
+// that LDS after the residual.
+template <int MT, int NT, bool CONTIG, bool RESID, int PREC, class TIN, class TOUT, bool WL>
 __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, int m0, int mcount,
                                                          FiberOut out, double *partials,
-                                                         int stage) {
+                                                         int stage, int wld) {
+  extern __shared__ double lds_raw[];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int64_t mbeg = (int64_t)m0 + (int64_t)blockIdx.y * (16 * MT);
@@ -287,51 +394,23 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
     fib[nt] = fwave + 16 * nt + col;
     base[nt] = fiber_base(in, fib[nt]);
   }
+  FiberW wv = w;
+  int64_t pm0 = mbeg, pmend = mend;
+  if constexpr (WL) {
+    stage_w<MT, PREC>(w, mbeg, mend, in.n, wld, lds_raw, wv);
+    pm0 = 0;
+    pmend = mend - mbeg;
+  }
   AccT<PREC> acc[MT][NT];
   double x2 = 0.0, e2 = 0.0;
-  project_wave<MT, NT, CONTIG, PREC, RESID, TIN>(in, w, mbeg, mend, base, acc, x2);
-
-  if (stage) {
-    extern __shared__ double stage_raw[];
-    constexpr int TW = 16 * MT;  // outputs per fibre in this block
-    constexpr int TWP = TW + 1;  // padded LDS row (odd: spreads the banks)
-    TOUT *tile = reinterpret_cast<TOUT *>(stage_raw) + (size_t)wid * (16 * NT) * TWP;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          tile[(16 * nt + col) * TWP + 16 * mt + acc_row<PREC>(grp, v)] = (TOUT)acc[mt][nt][v];
-    __syncthreads();
-    const int64_t mlen = (mend - mbeg) < TW ? (mend - mbeg) : TW;
-    const int64_t total = (int64_t)(16 * NT) * mlen;
-    for (int64_t idx = lane; idx < total; idx += 64) {
-      const int64_t fl = idx / mlen, ml = idx - fl * mlen;
-      const int64_t f = fwave + fl;
-      if (f < in.F) op[mbeg + ml + out.mo * f] = tile[fl * TWP + ml];
-    }
-  } else {
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int64_t f = fib[nt];
-      if (f >= in.F) continue;
-      const int64_t fq = f / out.ao, fr = f - fq * out.ao;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t m = mbeg + 16 * mt + acc_row<PREC>(grp, v);
-          if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (TOUT)acc[mt][nt][v];
-        }
-    }
-  }
+  project_wave<MT, NT, CONTIG, PREC, RESID, TIN>(in, wv, pm0, pmend, base, acc, x2);
 
   if constexpr (RESID) {
+    // (with RESID, m0 == 0 and the block holds all mcount rows of W)
     const int jtiles = (int)((in.n + 15) / 16);
     for (int jt = 0; jt < jtiles; ++jt) {
       AccT<PREC> racc[NT];
-      recon_tile<MT, NT, PREC>(w, mcount, in.n, jt, acc, racc);
+      recon_tile<MT, NT, PREC>(wv, mcount, in.n, jt, acc, racc);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (fib[nt] >= in.F) continue;
@@ -351,13 +430,55 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t j = 16 * jt + acc_row<PREC>(grp, v);
-          if (j < in.n) {
-            const double e = (double)xp[base[nt] + in.a * j] - (double)racc[nt][v];
-            e2 += e * e;
-          }
+          const bool ok = j < in.n;
+          const double xj = (double)load_or0(xp, base[nt] + in.a * j, ok);
+          const double e = ok ? xj - (double)racc[nt][v] : 0.0;
+          e2 += e * e;
         }
       }
     }
+  }
+
+  if (stage) {
+    if constexpr (WL) __syncthreads();  // every wave is done with the W copy
+    constexpr int TW = 16 * MT;  // outputs per fibre in this block
+    constexpr int TWP = TW + 1;  // padded LDS row (odd: spreads the banks)
+    TOUT *tile = reinterpret_cast<TOUT *>(lds_raw) + (size_t)wid * (16 * NT) * TWP;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          tile[(16 * nt + col) * TWP + 16 * mt + acc_row<PREC>(grp, v)] = (TOUT)acc[mt][nt][v];
+    __syncthreads();
+    const int mlen = (int)((mend - mbeg) < TW ? (mend - mbeg) : TW);
+    const int total = 16 * NT * mlen;
+    const float inv = 1.0f / (float)mlen;
+    for (int idx = lane; idx < total; idx += 64) {
+      int fl, ml;
+      tile_rc(idx, mlen, inv, fl, ml);
+      const int64_t f = fwave + fl;
+      if (f < in.F) op[mbeg + ml + out.mo * f] = tile[fl * TWP + ml];
+    }
+  } else {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int64_t f = fib[nt];
+      if (f >= in.F) continue;
+      int64_t fq, fr;
+      divmod_index(f, out.ao, fq, fr);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = mbeg + 16 * mt + acc_row<PREC>(grp, v);
+          if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (TOUT)acc[mt][nt][v];
+        }
+    }
+  }
+
+  if constexpr (RESID) {
     __shared__ double red[2][4];
     e2 = wave_sum(e2);
     x2 = wave_sum(x2);
@@ -503,9 +624,12 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
         for (int v = 0; v < 4; ++v)
           tile[(16 * nt + col) * TWP + 16 * mt + acc_row<PREC>(grp, v)] = (TOUT)acc[mt][nt][v];
     __syncthreads();
-    const int64_t total = (int64_t)(16 * NT) * mend;
-    for (int64_t idx = lane; idx < total; idx += 64) {
-      const int64_t fl = idx / mend, ml = idx - fl * mend;
+    const int mlen = (int)mend;
+    const int total = 16 * NT * mlen;
+    const float inv = 1.0f / (float)mlen;
+    for (int idx = lane; idx < total; idx += 64) {
+      int fl, ml;
+      tile_rc(idx, mlen, inv, fl, ml);
       const int64_t f = fwave + fl;
       if (f < in.F) op[ml + out.mo * f] = tile[fl * TWP + ml];
     }
@@ -514,7 +638,8 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
     for (int nt = 0; nt < NT; ++nt) {
       const int64_t f = fib[nt];
       if (f >= in.F) continue;
-      const int64_t fq = f / out.ao, fr = f - fq * out.ao;
+      int64_t fq, fr;
+    divmod_index(f, out.ao, fq, fr);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -639,8 +764,21 @@ hipError_t launch_fiber_t(const FiberIn &in, const FiberW &w, int m0, int mcount
   // tile fits (4 waves x 16 NT fibres x 16 MT outputs)
   const size_t lds = (size_t)4 * 16 * NT * (16 * MT + 1) * sizeof(TOUT);
   const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
-  hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT>), grid,
-                     dim3(kThreads), stage ? lds : 0, s, in, w, m0, mcount, out, partials, stage);
+  const size_t slds = stage ? lds : 0;
+  if constexpr (RESID) {
+    // the fused residual reads W twice: from an LDS copy when it fits
+    const int wld = w_lds_stride<PREC>(in.n);
+    const size_t wb = w_lds_bytes<MT, PREC>(wld);
+    if (wb <= 64 * 1024) {
+      hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT, true>), grid,
+                         dim3(kThreads), wb > slds ? wb : slds, s, in, w, m0, mcount, out,
+                         partials, stage, wld);
+      if (nparts) *nparts = (int)grid.x;
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT, false>), grid,
+                     dim3(kThreads), slds, s, in, w, m0, mcount, out, partials, stage, 0);
   if (nparts) *nparts = (int)grid.x;
   return hipGetLastError();
 }

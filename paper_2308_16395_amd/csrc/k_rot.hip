@@ -192,7 +192,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   for (int nt = 0; nt < NT; ++nt) {
     const int64_t f = fib[nt];
     if (f >= in.F) continue;
-    const int64_t fq = f / out.ao, fr = f - fq * out.ao;
+    int64_t fq, fr;
+    divmod_index(f, out.ao, fq, fr);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
