@@ -41,15 +41,42 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
   double q2 = 0.0;
   const bool vec = a.map.identity && (a.ldv & 1) == 0;
 
+  // Full tiles of an identity-mapped V with even ld are read as double2:
+  // thread t takes rows 2 (t % (TR/2)) .. +1 of columns t / (TR/2) + (512/TR) it.
+  // When every thread's columns fit KP registers, the next tile of the block is
+  // loaded into registers while the current one is processed.
+  constexpr int TPC = TR / 2, CPI = 256 / TPC, KP = 18;
+  const int rq = (tid % TPC) * 2, jq = tid / TPC;
+  const bool pre_ok = vec && (r + CPI - 1) / CPI <= KP;
+  double2 pre[KP];
+  auto prefetch = [&](int64_t row0) {
+#pragma unroll
+    for (int it = 0; it < KP; ++it) {
+      const int j = jq + CPI * it;
+      if (j < r) pre[it] = *reinterpret_cast<const double2 *>(a.V + row0 + rq + a.ldv * (int64_t)j);
+    }
+  };
   const int64_t ntiles = (a.R + TR - 1) / TR;
+  bool have_pre = pre_ok && (int64_t)blockIdx.x * TR + TR <= a.R;
+  if (have_pre) prefetch((int64_t)blockIdx.x * TR);
   for (int64_t tile_i = blockIdx.x; tile_i < ntiles; tile_i += gridDim.x) {
     const int64_t row0 = tile_i * TR;
     __syncthreads();
-    if (vec && row0 + TR <= a.R) {
-      // thread t: rows 2 (t % (TR/2)) .. +1 of columns t / (TR/2) + (512/TR) it
-      constexpr int TPC = TR / 2, CPI = 256 / TPC;
-      const int rq = (tid % TPC) * 2;
-      for (int j = tid / TPC; j < r; j += CPI) {
+    if (have_pre) {
+#pragma unroll
+      for (int it = 0; it < KP; ++it) {
+        const int j = jq + CPI * it;
+        if (j < r) {
+          double *t = tile + j * LDT + rq;
+          t[0] = pre[it].x;
+          t[1] = pre[it].y;
+        }
+      }
+      const int64_t nrow0 = (tile_i + gridDim.x) * TR;
+      have_pre = nrow0 + TR <= a.R;
+      if (have_pre) prefetch(nrow0);
+    } else if (vec && row0 + TR <= a.R) {
+      for (int j = jq; j < r; j += CPI) {
         const double2 v2 =
             *reinterpret_cast<const double2 *>(a.V + row0 + rq + a.ldv * (int64_t)j);
         double *t = tile + j * LDT + rq;
@@ -759,12 +786,16 @@ hipError_t launch_ud_row64(const double *Ud, int64_t ld, int64_t t, int rd, cons
 
 // ---------------------------------------------------------------------------
 // V0^T x for a tall column-major V0 (R x r): lanes run over rows (coalesced
-// column segments, no LDS), each lane keeps its RPL entries of x in registers,
-// and the four waves of a block split the columns. Block b covers rows
-// [64 RPL b, 64 RPL (b + 1)) and writes part[j * nb + b] (j < r) and
-// part[r * nb + b] = sum of x^2 over its rows.
+// column segments, no LDS). Block (bx, by) covers rows [kGemvRows bx,
+// kGemvRows (bx + 1)) and columns [16 by, 16 by + 16), four per wave; each lane
+// accumulates its kGemvRPL rows of every chunk in registers, so one wave
+// reduction per column and block serves kGemvRows rows. The block writes
+// part[j * nb + bx] (j < r), and blocks with by == 0 also part[r * nb + bx] =
+// sum of x^2 over their rows.
 // ---------------------------------------------------------------------------
-constexpr int kGemvRPL = 8;
+constexpr int kGemvRPL = 8;                          // rows per lane and chunk
+constexpr int kGemvChunks = 4;                       // chunks per block
+constexpr int kGemvRows = 64 * kGemvRPL * kGemvChunks;  // 2048 rows per block
 
 // MAPPED: V0 is stored at the old ranks (ld = ldv rows) and row i of the new
 // layout reads old row map(i), or is zero for a padded row.
@@ -774,29 +805,34 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t l
                                                      double *part) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nb = gridDim.x;
-  const int64_t row0 = (int64_t)blockIdx.x * 64 * kGemvRPL + lane;
-  const bool full = !MAPPED && (int64_t)(blockIdx.x + 1) * 64 * kGemvRPL <= R;
-  double xv[kGemvRPL];
-  int64_t src[kGemvRPL];
+  const int j0 = ((int)blockIdx.y * 4 + wid) * 4;  // this wave's four columns
+  const bool norms = blockIdx.y == 0 && wid == 0;
+  if (j0 >= r && !norms) return;
+  const int64_t rowb = (int64_t)blockIdx.x * kGemvRows;
+  const bool full = !MAPPED && rowb + kGemvRows <= R;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
   double xx = 0.0;
+  for (int ch = 0; ch < kGemvChunks; ++ch) {
+    const int64_t row0 = rowb + (int64_t)ch * 64 * kGemvRPL + lane;
+    double xv[kGemvRPL];
+    int64_t src[kGemvRPL];
 #pragma unroll
-  for (int i = 0; i < kGemvRPL; ++i) {
-    const int64_t row = row0 + 64 * i;
-    xv[i] = row < R ? x[row] : 0.0;
-    xx += xv[i] * xv[i];
-    src[i] = row < R ? (MAPPED ? map_new_to_old(map, row) : row) : -1;
-  }
-  // four columns per wave and iteration: 4 kGemvRPL loads in flight per lane
-  // before the reductions
-  constexpr int CPI = 4;
-  for (int j0 = wid * CPI; j0 < r; j0 += 4 * CPI) {
-    double s[CPI];
+    for (int i = 0; i < kGemvRPL; ++i) {
+      const int64_t row = row0 + 64 * i;
+      const double v = x[row < R ? row : 0];
+      xv[i] = row < R ? v : 0.0;
+      src[i] = row < R ? (MAPPED ? map_new_to_old(map, row) : row) : -1;
+    }
+    if (norms) {
 #pragma unroll
-    for (int c = 0; c < CPI; ++c) {
+      for (int i = 0; i < kGemvRPL; ++i) xx += xv[i] * xv[i];
+    }
+    if (j0 >= r) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
       // columns past r repeat column j0 and are not stored
       const int j = (j0 + c < r) ? j0 + c : j0;
       const double *col = V0 + ldv * (int64_t)j;
-      s[c] = 0.0;
       if (full) {
 #pragma unroll
         for (int i = 0; i < kGemvRPL; ++i) s[c] += col[row0 + 64 * i] * xv[i];
@@ -808,20 +844,22 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t l
         }
       }
     }
+  }
+  if (j0 < r) {
 #pragma unroll
-    for (int c = 0; c < CPI; ++c) {
+    for (int c = 0; c < 4; ++c) {
       const double t = wave_sum(s[c]);
       if (lane == 0 && j0 + c < r) part[(size_t)(j0 + c) * nb + blockIdx.x] = t;
     }
   }
-  if (wid == 0) {
+  if (norms) {
     xx = wave_sum(xx);
     if (lane == 0) part[(size_t)r * nb + blockIdx.x] = xx;
   }
 }
 
 int gemv_t_blocks(int64_t R) {
-  const int64_t t = (R + 64 * kGemvRPL - 1) / (64 * kGemvRPL);
+  const int64_t t = (R + kGemvRows - 1) / kGemvRows;
   return (int)(t > 0 ? t : 1);
 }
 
@@ -829,16 +867,16 @@ hipError_t launch_gemv_t(const double *V0, int64_t R, int r, const double *x, do
                          int nb, hipStream_t s) {
   RowMap ident{};
   ident.identity = 1;
-  hipLaunchKernelGGL(gemv_t_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, V0, R, ident, R,
-                     r, x, part);
+  hipLaunchKernelGGL(gemv_t_kernel<false>, dim3((unsigned)nb, (unsigned)(r > 0 ? (r + 15) / 16 : 1)), dim3(256),
+                     0, s, V0, R, ident, R, r, x, part);
   return hipGetLastError();
 }
 
 hipError_t launch_gemv_t_mapped(const double *V, int64_t ldv, const RowMap &map, int64_t R, int r,
                                 const double *x, double *part, int nb, hipStream_t s) {
   if (map.identity) return launch_gemv_t(V, R, r, x, part, nb, s);
-  hipLaunchKernelGGL(gemv_t_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, V, ldv, map, R, r,
-                     x, part);
+  hipLaunchKernelGGL(gemv_t_kernel<true>, dim3((unsigned)nb, (unsigned)(r > 0 ? (r + 15) / 16 : 1)), dim3(256),
+                     0, s, V, ldv, map, R, r, x, part);
   return hipGetLastError();
 }
 
