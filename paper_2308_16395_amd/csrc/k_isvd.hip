@@ -898,20 +898,64 @@ __device__ inline void mv_trans(const double *M, int r, const double *x, double 
     for (int i = threadIdx.x; i < r; i += blockDim.x) y[i] = x[i];
     return;
   }
+  // four outputs per wave and iteration: their loads are in flight together
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wid; i < r; i += nw) {
-    const double *mc = M + (size_t)r * i;
-    double a = 0.0;
-    for (int l = lane; l < r; l += 64) a += mc[l] * x[l];
-    a = wave_sum(a);
-    if (lane == 0) y[i] = a;
+  for (int i0 = 4 * wid; i0 < r; i0 += 4 * nw) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = lane; l < r; l += 64) {
+      const double xl = x[l];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = (i0 + c < r) ? i0 + c : i0;
+        a[c] += M[l + (size_t)r * i] * xl;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double t = wave_sum(a[c]);
+      if (lane == 0 && i0 + c < r) y[i0 + c] = t;
+    }
   }
 }
 
-// y = M x: one thread per output, consecutive threads on consecutive rows
-__device__ inline void mv_plain(const double *M, int r, const double *x, double *y) {
+// y = M x (M column-major r x r). For r <= kMvRows the block's 16 waves split
+// the columns l (wave w takes l = w, w + 16, ...) and the lanes the rows, so
+// all loads of a wave are independent; the 16 partial vectors are summed in
+// LDS. Larger r: one thread per output row.
+constexpr int kMvRows = 256;
+__device__ inline void mv_plain(const double *M, int r, const double *x, double *y,
+                                double (*part)[kMvRows]) {
   if (!M) {
     for (int i = threadIdx.x; i < r; i += blockDim.x) y[i] = x[i];
+    return;
+  }
+  if (r <= kMvRows && blockDim.x == 1024) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double a[kMvRows / 64];
+#pragma unroll
+    for (int c = 0; c < kMvRows / 64; ++c) a[c] = 0.0;
+    for (int l = wid; l < r; l += 16) {
+      const double xl = x[l];
+      const double *mc = M + (size_t)r * l;
+#pragma unroll
+      for (int c = 0; c < kMvRows / 64; ++c) {
+        const int i = lane + 64 * c;
+        if (i < r) a[c] += mc[i] * xl;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kMvRows / 64; ++c) {
+      const int i = lane + 64 * c;
+      if (i < r) part[wid][i] = a[c];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += blockDim.x) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) t += part[w][i];
+      y[i] = t;
+    }
+    __syncthreads();
     return;
   }
   for (int i = threadIdx.x; i < r; i += blockDim.x) {
@@ -928,12 +972,13 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
                                                          double *p, double *ws, double *sc,
                                                          double *g, double *ge) {
   __shared__ double red[16];
+  __shared__ double part[16][kMvRows];
   const int tid = threadIdx.x;
   mv_trans(M, r, t1, p1);
   __syncthreads();
-  mv_plain(M, r, p1, w1);
+  mv_plain(M, r, p1, w1, part);
   __syncthreads();
-  mv_plain(G0, r, w1, g);  // G0 is symmetric
+  mv_plain(G0, r, w1, g, part);  // G0 is symmetric
   __syncthreads();
   double a1 = 0.0, a2 = 0.0;
   for (int i = tid; i < r; i += blockDim.x) {
@@ -948,9 +993,9 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
   mv_trans(M, r, t2, p2);
   __syncthreads();
   for (int i = tid; i < r; i += blockDim.x) p[i] = p1[i] + p2[i];
-  mv_plain(M, r, p2, w2);
+  mv_plain(M, r, p2, w2, part);
   __syncthreads();
-  mv_plain(G0, r, w2, g);
+  mv_plain(G0, r, w2, g, part);
   __syncthreads();
   double b1 = 0.0, b2 = 0.0;
   for (int i = tid; i < r; i += blockDim.x) {
