@@ -171,10 +171,11 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
 // for k < n; element n: none (extra_mode 0), extra[f] (1), or
 // extra[f] - sum_{k<n} X[f][k] pvec[k] formed in FP64 (2).
 // `w64` selects FP64 X, W and P; otherwise all three are FP32 (the output is
-// rounded once).
+// rounded once). With `f32m` (FP32 only) the products run on the FP32 MFMA with
+// FP32 sums inside each 32-wide K block and FP64 sums across blocks.
 hipError_t launch_rot64(const FiberIn &in, const void *w, int w64, int64_t ldw, int m0,
                         int mcount, const FiberOut &out, int extra_mode, const double *pvec,
-                        hipStream_t s);
+                        hipStream_t s, int f32m = 0);
 
 // Gram of the residual E = X - (X x W^T) x W (or of X itself when rows == 0)
 // over all fibres, summed in FP64 in a fixed order into G (n x n,

@@ -771,8 +771,10 @@ int st_handle::do_update(const float *y) {
   cin.x64 = 0;
   cin.extra = dvec;
   tic();
+  // the FP32 and bf16x3 forms take the FP32 MFMA with FP64 sums across K blocks
+  // (the core never enters a rank test); the FP64 form keeps exact products
   e = launch_rot64(cin, Wc.p, 0, ldwc, 0, (int)c, FiberOut{C[nxt].p, 0, Rnew, c}, 1, nullptr,
-                   stream);
+                   stream, prec == Prec::FP64 ? 0 : 1);
   // read C (FP32) and d (FP64), write C~ (FP32)
   toc(ST_K_ROT_C, 2.0 * Rnew * (double)(rd + 1) * c,
       4.0 * ((double)Rold * rd + (double)Rnew * c) + 8.0 * Rnew);

@@ -27,7 +27,11 @@ using namespace fk;
 template <class T, int MT>
 constexpr bool kRotPrefetchW = std::is_same<T, float>::value && MT <= 11;
 
-template <int MT, int NT, int EXTRA, class T>
+// F32M (FP32 core only): the products run on the FP32 MFMA, summed in FP32
+// within each 32-wide K block (eight MFMA steps), and the block sums are added
+// in FP64. Each output then carries about one FP32 rounding per K block on top
+// of the final rounding to FP32, instead of exact products.
+template <int MT, int NT, int EXTRA, class T, bool F32M>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void rot_kernel(
     FiberIn in, const T *w, int64_t ldw, int m0, int mcount, FiberOut out, const double *pvec) {
   constexpr int LDW = std::is_same<T, double>::value ? 33 : 36;  // LDS row stride of W
@@ -47,11 +51,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     fib[nt] = fwave + 16 * nt + col;
     base[nt] = fib[nt] < in.F ? map_new_to_old(in.map, fib[nt]) : -1;
   }
-  f64x4 acc[MT][NT];
+  static_assert(!F32M || std::is_same<T, float>::value, "FP32 MFMA for the FP32 core only");
+  using AccV = typename std::conditional<F32M, f32x4, f64x4>::type;
+  AccV acc[MT][NT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = AccV{0, 0, 0, 0};
+  // F32M: FP64 totals of the per-block FP32 sums (rows 4 grp + v)
+  double tot[F32M ? MT : 1][F32M ? NT : 1][4];
+#pragma unroll
+  for (int mt = 0; mt < (F32M ? MT : 1); ++mt)
+#pragma unroll
+    for (int nt = 0; nt < (F32M ? NT : 1); ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tot[mt][nt][v] = 0.0;
+  auto flush = [&]() {
+    if constexpr (F32M) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) tot[mt][nt][v] += (double)acc[mt][nt][v];
+          acc[mt][nt] = AccV{0, 0, 0, 0};
+        }
+    }
+  };
   double dot[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) dot[nt] = 0.0;
@@ -82,7 +108,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int wc = threadIdx.x & 31, wr0 = threadIdx.x >> 5;
   // Where the registers allow (PW), the W slice of the next block is fetched
   // with the X prefetch; otherwise it is loaded at the top of its own block.
-  constexpr bool PW = kRotPrefetchW<T, MT>;
+  constexpr bool PW = kRotPrefetchW<T, MT> && !F32M;
   T wv[WPT];
   auto load_w = [&](int64_t kb) {
     const int64_t kk = (kb + wc < K) ? kb + wc : 0;
@@ -145,8 +171,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            acc[mt][nt] = mfma_f64((double)wa[s & 1][mt], xd[nt][s], acc[mt][nt]);
+          for (int nt = 0; nt < NT; ++nt) {
+            if constexpr (F32M)
+              acc[mt][nt] = mfma4((float)wa[s & 1][mt], (float)xd[nt][s], acc[mt][nt]);
+            else
+              acc[mt][nt] = mfma_f64((double)wa[s & 1][mt], xd[nt][s], acc[mt][nt]);
+          }
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -160,6 +190,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     double xd[NT][8];
     stage(kb, xd);
     steps(8, xd);
+    flush();
   }
   if (kmain < K) {
     double xd[NT][8];
@@ -187,6 +218,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
     // steps wholly past K are skipped
     steps((int)((K - kmain + 3) >> 2), xd);
+    flush();
   }
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
@@ -198,46 +230,56 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t m = mbeg + 16 * mt + acc_row<2>(grp, v);
-        if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (T)acc[mt][nt][v];
+        if constexpr (F32M) {
+          const int64_t m = mbeg + 16 * mt + acc_row<0>(grp, v);
+          if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (T)tot[mt][nt][v];
+        } else {
+          const int64_t m = mbeg + 16 * mt + acc_row<2>(grp, v);
+          if (m < mend) op[fr + out.ao * (m + out.mo * fq)] = (T)acc[mt][nt][v];
+        }
       }
   }
 }
 
 template <int MT, int NT, class T>
 hipError_t launch_rot_t(const FiberIn &in, const T *w, int64_t ldw, int m0, int mcount,
-                        const FiberOut &out, int extra_mode, const double *pvec, hipStream_t s) {
+                        const FiberOut &out, int extra_mode, const double *pvec, int f32m,
+                        hipStream_t s) {
   const int64_t per_block = 64 * NT;
   dim3 grid((unsigned)((in.F + per_block - 1) / per_block),
             (unsigned)((mcount + 16 * MT - 1) / (16 * MT)));
   if constexpr (std::is_same<T, double>::value) {
     // the auxiliary matrix: no extra column, or the complement column
     if (extra_mode == 2)
-      hipLaunchKernelGGL((rot_kernel<MT, NT, 2, T>), grid, dim3(kThreads), 0, s, in, w, ldw, m0,
+      hipLaunchKernelGGL((rot_kernel<MT, NT, 2, T, false>), grid, dim3(kThreads), 0, s, in, w, ldw, m0,
                          mcount, out, pvec);
     else if (extra_mode == 0)
-      hipLaunchKernelGGL((rot_kernel<MT, NT, 0, T>), grid, dim3(kThreads), 0, s, in, w, ldw, m0,
+      hipLaunchKernelGGL((rot_kernel<MT, NT, 0, T, false>), grid, dim3(kThreads), 0, s, in, w, ldw, m0,
                          mcount, out, pvec);
     else
       return hipErrorInvalidValue;
   } else {
     // the core: the new row d^T
     if (extra_mode != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((rot_kernel<MT, NT, 1, T>), grid, dim3(kThreads), 0, s, in, w, ldw, m0,
-                       mcount, out, pvec);
+    if (f32m)
+      hipLaunchKernelGGL((rot_kernel<MT, NT, 1, T, true>), grid, dim3(kThreads), 0, s, in, w, ldw,
+                         m0, mcount, out, pvec);
+    else
+      hipLaunchKernelGGL((rot_kernel<MT, NT, 1, T, false>), grid, dim3(kThreads), 0, s, in, w,
+                         ldw, m0, mcount, out, pvec);
   }
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_rot_typed(const FiberIn &in, const T *w, int64_t ldw, int m0, int mcount,
-                            const FiberOut &out, int extra_mode, const double *pvec,
+                            const FiberOut &out, int extra_mode, const double *pvec, int f32m,
                             hipStream_t s) {
   // the smallest instantiated column-tile count that covers mcount (padding
   // columns cost whole MFMAs); wider outputs take several column blocks
   const int tiles = (mcount + 15) / 16;
 #define ST_ROT_CASE(T_, NT_) \
-  if (tiles <= T_) return launch_rot_t<T_, NT_, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+  if (tiles <= T_) return launch_rot_t<T_, NT_, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, f32m, s);
   // narrow outputs reuse each staged W value for two fibre tiles; wide ones
   // keep one fibre tile per wave so that the accumulators fit two waves per SIMD
   constexpr int NT6 = std::is_same<T, double>::value ? 1 : 2;
@@ -249,23 +291,23 @@ hipError_t launch_rot_typed(const FiberIn &in, const T *w, int64_t ldw, int m0, 
   ST_ROT_CASE(10, 1)
   ST_ROT_CASE(11, 1)
 #undef ST_ROT_CASE
-  return launch_rot_t<12, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, s);
+  return launch_rot_t<12, 1, T>(in, w, ldw, m0, mcount, out, extra_mode, pvec, f32m, s);
 }
 
 }  // namespace
 
 hipError_t launch_rot64(const FiberIn &in, const void *w, int w64, int64_t ldw, int m0,
                         int mcount, const FiberOut &out, int extra_mode, const double *pvec,
-                        hipStream_t s) {
+                        hipStream_t s, int f32m) {
   if (in.F <= 0 || mcount <= 0) return hipSuccess;
   if (!in.mapped || (extra_mode != 0 && in.extra == nullptr) || (extra_mode == 2 && !pvec))
     return hipErrorInvalidValue;
   if ((in.x64 != 0) != (w64 != 0) || (out.o64 != 0) != (w64 != 0)) return hipErrorInvalidValue;
   if (w64)
     return launch_rot_typed<double>(in, static_cast<const double *>(w), ldw, m0, mcount, out,
-                                    extra_mode, pvec, s);
+                                    extra_mode, pvec, 0, s);
   return launch_rot_typed<float>(in, static_cast<const float *>(w), ldw, m0, mcount, out,
-                                 extra_mode, pvec, s);
+                                 extra_mode, pvec, f32m, s);
 }
 
 }  // namespace st
