@@ -137,6 +137,7 @@ struct st_handle {
 
   // work buffers
   DBuf<double> D[2];   // partial cores D*_k of the update (FP64)
+  DBuf<double> Dspec[ST_MAX_MODES], specpart, specsums;  // the no-growth pass over all modes
   DBuf<float> RB[2], wrow;  // reconstruction work
   DBuf<double> part, sums;
   DBuf<double> gram_part;
@@ -544,7 +545,64 @@ int st_handle::do_update(const float *y) {
   int dsel = 0;
   double delta2 = 0.0, eps = 0.0, ynorm2 = 0.0;
   int rc;
-  for (int k = 0; k < m; ++k) {
+  // Every mode is first projected at the current ranks, the case of no growth
+  // (Alg. 4 keeping U_k for every k), and the residual norms of all modes come
+  // back with one synchronisation. From the first mode whose test fails or
+  // falls in the guard band, the modes are redone one at a time below.
+  int k0 = 0;
+  {
+    size_t poff[ST_MAX_MODES + 1];
+    poff[0] = 0;
+    for (int k = 0; k < m; ++k)
+      poff[k + 1] = poff[k] + 2 * (size_t)fiber_max_blocks(rprod(r, k) * nprod(k + 1));
+    e = specpart.ensure(poff[m]);
+    if (e == hipSuccess) e = specsums.ensure(2 * (size_t)m);
+    for (int k = 0; k < m && e == hipSuccess; ++k)
+      e = Dspec[k].ensure((size_t)(rprod(r, k) * nprod(k + 1) * r[k]));
+    if (e != hipSuccess) return hipfail(e, "mode buffers");
+    const void *x = y;
+    int x64 = 0;
+    for (int k = 0; k < m; ++k) {
+      const int64_t a = rprod(r, k), nk = n[k], b = nprod(k + 1);
+      FiberIn in{};
+      in.x = x;
+      in.x64 = x64;
+      in.a = a;
+      in.n = nk;
+      in.F = a * b;
+      int nb = 0;
+      tic();
+      e = launch_fiber_project(in, wmat(k), 0, (int)r[k], FiberOut{Dspec[k].p, 1, a, r[k]},
+                               specpart.p + poff[k], prec, stream, &nb);
+      toc(k == 0 ? ST_K_TTM1 : ST_K_TTM, 4.0 * in.F * nk * r[k], 4.0 * in.F * (nk + r[k]));
+      if (e == hipSuccess) e = launch_reduce_pairs(specpart.p + poff[k], nb, specsums.p + 2 * k,
+                                                   stream);
+      if (e != hipSuccess) return hipfail(e, "fiber projection + residual");
+      x = Dspec[k].p;
+      x64 = 1;
+    }
+    e = hipMemcpyAsync(hpin, specsums.p, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost,
+                       stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "residual norms");
+    settle();
+    ynorm2 = hpin[1];
+    if (!std::isfinite(ynorm2)) return fail(ST_ENONFINITE, "slice is not finite");
+    eps = tau * std::sqrt(ynorm2 / d);
+    for (k0 = 0; k0 < m; ++k0) {
+      const double e2 = hpin[2 * k0];
+      if (!std::isfinite(e2)) return fail(ST_ENONFINITE, "non-finite residual in mode %d", k0 + 1);
+      const double en = std::sqrt(e2);
+      if (en > eps || (prec != Prec::FP64 && std::fabs(en - eps) <= guard_rel * eps)) break;
+      stt.e_norm[k0] = en;
+      delta2 += e2;
+    }
+    if (k0 > 0) {
+      Din = Dspec[k0 - 1].p;
+      din64 = 1;
+    }
+  }
+  for (int k = k0; k < m; ++k) {
     const int64_t a = rprod(rn, k);
     const int64_t nk = n[k];
     const int64_t b = nprod(k + 1);
@@ -1106,6 +1164,9 @@ void st_handle::destroy() {
     D[i].release();
     RB[i].release();
   }
+  for (int k = 0; k < ST_MAX_MODES; ++k) Dspec[k].release();
+  specpart.release();
+  specsums.release();
   wrow.release();
   tvec.release();
   wvec.release();
