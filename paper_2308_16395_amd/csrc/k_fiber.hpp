@@ -359,11 +359,11 @@ __device__ inline void stage_w(const FiberW &w, int64_t mbeg, int64_t mend, int6
 // reads of FP32 rows) or 8 (bf16x8 reads), padded so that consecutive rows
 // start in different banks.
 template <int PREC>
-inline int w_lds_stride(int64_t n) {
+__host__ __device__ inline int w_lds_stride(int64_t n) {
   return PREC == 1 ? (int)(((n + 7) / 8) * 8 + 8) : (int)(((n + 7) / 8) * 8 + 4);
 }
 template <int MT, int PREC>
-inline size_t w_lds_bytes(int wld) {
+__host__ __device__ inline size_t w_lds_bytes(int wld) {
   // bf16x3 keeps the hi and lo halves (2 x 2 bytes per element)
   return (size_t)16 * MT * wld * (PREC == 2 ? 8 : 4);
 }
@@ -541,10 +541,11 @@ __device__ constexpr int kidx(int i, int grp, int v) {
   return 16 * i + (PREC == 2 ? grp + 4 * v : 4 * grp + v);
 }
 
-template <int MT, int NT, int JT, int PREC, class TIN, class TOUT>
+template <int MT, int NT, int JT, int PREC, class TIN, class TOUT, bool WL>
 __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, int mcount,
                                                          FiberOut out, double *partials,
-                                                         int stage) {
+                                                         int stage, int wld) {
+  extern __shared__ double stage_raw[];
   // element type kept in registers: the input's, or FP64 for the FP64 MFMA
   using XT = typename std::conditional<PREC == 2 || std::is_same<TIN, double>::value, double,
                                        float>::type;
@@ -560,6 +561,14 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
   for (int nt = 0; nt < NT; ++nt) {
     fib[nt] = fwave + 16 * nt + col;
     base[nt] = fiber_base(in, fib[nt]);
+  }
+  // WL: W (all mcount rows) is read from an LDS copy, with the output tile
+  // after it in LDS
+  FiberW wv = w;
+  size_t tile_off = 0;  // doubles
+  if constexpr (WL) {
+    stage_w<MT, PREC>(w, 0, mcount, n, wld, stage_raw, wv);
+    tile_off = (w_lds_bytes<MT, PREC>(wld) + 15) / 16 * 2;
   }
   XT x[NT][JT][4];
   double x2 = 0.0;
@@ -602,8 +611,8 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t k0 = kidx<PREC>(i0, grp, v), k1 = kidx<PREC>(i0 + 1, grp, v);
-          t[v] = load_or0(w.w, m * w.ldw + k0, m < mcount && k0 < n);
-          t[4 + v] = load_or0(w.w, m * w.ldw + k1, i0 + 1 < JT && m < mcount && k1 < n);
+          t[v] = load_or0(wv.w, m * wv.ldw + k0, m < mcount && k0 < n);
+          t[4 + v] = load_or0(wv.w, m * wv.ldw + k1, i0 + 1 < JT && m < mcount && k1 < n);
         }
         bf16x8 wh, wl;
         split8(t, wh, wl);
@@ -626,12 +635,12 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
           const int m = 16 * mt + col;
           const bool ok = m < mcount && k < n;
           if constexpr (PREC == 2) {
-            const double a = load_or0(w.w64, m * w.ldw + k, ok);
+            const double a = load_or0(wv.w64, m * wv.ldw + k, ok);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
               acc[mt][nt] = mfma_f64(a, (double)x[nt][i][v], acc[mt][nt]);
           } else {
-            const float a = load_or0(w.w, m * w.ldw + k, ok);
+            const float a = load_or0(wv.w, m * wv.ldw + k, ok);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
               acc[mt][nt] = mfma4(a, (float)x[nt][i][v], acc[mt][nt]);
@@ -643,10 +652,9 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
   // P = D x_k W^T (this block holds all rows of W)
   const int64_t mend = mcount;
   if (stage) {
-    extern __shared__ double stage_raw[];
     constexpr int TW = 16 * MT;
     constexpr int TWP = TW + 1;
-    TOUT *tile = reinterpret_cast<TOUT *>(stage_raw) + (size_t)wid * (16 * NT) * TWP;
+    TOUT *tile = reinterpret_cast<TOUT *>(stage_raw + tile_off) + (size_t)wid * (16 * NT) * TWP;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -686,7 +694,7 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
 #pragma unroll
   for (int i = 0; i < JT; ++i) {
     AccT<PREC> racc[NT];
-    recon_tile<MT, NT, PREC>(w, mcount, n, i, acc, racc);
+    recon_tile<MT, NT, PREC>(wv, mcount, n, i, acc, racc);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       if (fib[nt] >= in.F) continue;
@@ -713,29 +721,43 @@ __global__ __launch_bounds__(kThreads) void resid_kernel(FiberIn in, FiberW w, i
   }
 }
 
+template <int MT, int NT, int JT, int PREC, class TIN, class TOUT>
+hipError_t launch_resid_w(const FiberIn &in, const FiberW &w, int mcount, const FiberOut &out,
+                          double *partials, hipStream_t s, int *np) {
+  const size_t lds = (size_t)4 * 16 * NT * (16 * MT + 1) * sizeof(TOUT);
+  const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
+  const size_t slds = stage ? lds : 0;
+  dim3 grid((unsigned)((in.F + 64 * NT - 1) / (64 * NT)));
+  // W read from an LDS copy when it fits beside the output tile
+  const int wld = w_lds_stride<PREC>(in.n);
+  const size_t wb = (w_lds_bytes<MT, PREC>(wld) + 15) / 16 * 16;
+  if (wb + slds <= 96 * 1024) {
+    if (wb + slds > 64 * 1024) {
+      const void *fn = (const void *)resid_kernel<MT, NT, JT, PREC, TIN, TOUT, true>;
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(wb + slds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((resid_kernel<MT, NT, JT, PREC, TIN, TOUT, true>), grid, dim3(kThreads),
+                       wb + slds, s, in, w, mcount, out, partials, stage, wld);
+  } else {
+    hipLaunchKernelGGL((resid_kernel<MT, NT, JT, PREC, TIN, TOUT, false>), grid, dim3(kThreads),
+                       slds, s, in, w, mcount, out, partials, stage, 0);
+  }
+  if (np) *np = (int)grid.x;
+  return hipGetLastError();
+}
+
 template <int MT, int JT, int PREC, class TIN, class TOUT>
 hipError_t launch_resid_t(const FiberIn &in, const FiberW &w, int mcount, const FiberOut &out,
                           double *partials, hipStream_t s, int *np) {
   // two fibre tiles per wave when the registers allow it and there are enough
   // fibres to fill the chip
   constexpr bool wide = !(PREC == 2 || std::is_same<TIN, double>::value) && JT * MT <= 24;
-  if (wide && in.F >= 256 * 128) {
-    constexpr int NT = wide ? 2 : 1;
-    const size_t lds = (size_t)4 * 16 * NT * (16 * MT + 1) * sizeof(TOUT);
-    const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
-    dim3 grid((unsigned)((in.F + 64 * NT - 1) / (64 * NT)));
-    hipLaunchKernelGGL((resid_kernel<MT, NT, JT, PREC, TIN, TOUT>), grid, dim3(kThreads),
-                       stage ? lds : 0, s, in, w, mcount, out, partials, stage);
-    if (np) *np = (int)grid.x;
-  } else {
-    const size_t lds = (size_t)4 * 16 * (16 * MT + 1) * sizeof(TOUT);
-    const int stage = (out.ao == 1 && lds <= 64 * 1024) ? 1 : 0;
-    dim3 grid((unsigned)((in.F + 63) / 64));
-    hipLaunchKernelGGL((resid_kernel<MT, 1, JT, PREC, TIN, TOUT>), grid, dim3(kThreads),
-                       stage ? lds : 0, s, in, w, mcount, out, partials, stage);
-    if (np) *np = (int)grid.x;
-  }
-  return hipGetLastError();
+  if (wide && in.F >= 256 * 128)
+    return launch_resid_w<MT, wide ? 2 : 1, JT, PREC, TIN, TOUT>(in, w, mcount, out, partials, s,
+                                                                 np);
+  return launch_resid_w<MT, 1, JT, PREC, TIN, TOUT>(in, w, mcount, out, partials, s, np);
 }
 
 template <int MT, int JT, class TIN, class TOUT>
