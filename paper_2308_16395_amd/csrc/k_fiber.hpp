@@ -200,16 +200,20 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
       }
     }
   };
-  fetch(0);
+  // wide tiles (MT NT > 8) load in the iteration instead: the prefetch
+  // registers would cost them their second wave per SIMD
+  constexpr bool PF = MT * NT <= 8;
+  if (PF) fetch(0);
   for (int64_t kb = 0; kb < K; kb += 32) {
     const int64_t k0 = kb + 8 * grp;
+    if (!PF) fetch(kb);
     OpT<PREC> xv[NT][8];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int s = 0; s < 8; ++s)
         xv[nt][s] = ((xm >> (8 * nt + s)) & 1u) ? (OpT<PREC>)xr[nt][s] : (OpT<PREC>)0;
-    if (kb + 32 < K) fetch(kb + 32);
+    if (PF && kb + 32 < K) fetch(kb + 32);
     if (NORMX) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
@@ -409,7 +413,8 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
     // (with RESID, m0 == 0 and the block holds all mcount rows of W)
     const int jtiles = (int)((in.n + 15) / 16);
     bool fast = false;
-    if constexpr (CONTIG && PREC != 2 && std::is_same<TIN, float>::value) fast = in.n % 16 == 0;
+    if constexpr (CONTIG && PREC != 2 && std::is_same<TIN, float>::value && MT * NT <= 8)
+      fast = in.n % 16 == 0;
     if (fast) {
       // contiguous FP32 fibres, whole tiles: rows 16 jt + 4 grp .. + 3 of each
       // fibre in one 16-byte load, fetched one tile ahead of the reconstruction
