@@ -59,6 +59,11 @@ enum st_precision {
                      products, FP64 sums (the form that reproduces the FP64 rank
                      decisions; see the header of st_update) */
 };
+/* In every form V, the partial cores and the slice coordinates d are FP64 and
+   the rank tests are taken in FP64. The literal core rotation (FP32 core) runs
+   on the FP64 MFMA in ST_FP64 and on the FP32 MFMA in the other two forms, with
+   FP32 sums inside each 32-wide block of the contraction and FP64 sums across
+   blocks. */
 
 enum st_where { ST_HOST = 0, ST_DEVICE = 1 };
 
