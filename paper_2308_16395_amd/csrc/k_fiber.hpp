@@ -323,34 +323,64 @@ __device__ inline void recon_tile(const FiberW &w, int64_t rows, int64_t n, int 
 }
 
 // Copy rows [mbeg, min(mend, mbeg + 16 MT)) of W (all n columns, in the form
-// the product precision reads) into LDS with row stride wld and point wv at
-// the copy (rows then count from mbeg). Ends with a block barrier.
+// the product precision reads) into LDS with row stride wld, zero the rows up
+// to 16 MT (so every lane can take the vector reads), and point wv at the copy
+// (rows then count from mbeg). Thread t copies row t / 32 (+ 8 i), columns
+// 4 (t % 32) + 128 j as 16-byte vectors when the strides allow, else single
+// elements; no index division. Ends with a block barrier.
 template <int MT, int PREC>
 __device__ inline void stage_w(const FiberW &w, int64_t mbeg, int64_t mend, int64_t n, int wld,
                                double *lds, FiberW &wv) {
   const int rows = (int)((mend - mbeg) < 16 * MT ? (mend - mbeg) : 16 * MT);
-  const int nn = (int)n, total = rows * nn;
+  const int nn = (int)n, r0 = threadIdx.x >> 5, c0 = threadIdx.x & 31;
   if constexpr (PREC == 0) {
     float *d = reinterpret_cast<float *>(lds);
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-      const int r = idx / nn, k = idx - r * nn;
-      d[r * wld + k] = w.w[(mbeg + r) * w.ldw + k];
+    const bool v4 = (nn & 3) == 0 && (w.ldw & 3) == 0 && (wld & 3) == 0 &&
+                    ((uintptr_t)w.w & 15) == 0 && ((mbeg * w.ldw) & 3) == 0;
+    for (int r = r0; r < 16 * MT; r += 8) {
+      float *dr = d + r * wld;
+      if (r < rows) {
+        const float *src = w.w + (mbeg + r) * w.ldw;
+        if (v4) {
+          for (int k = 4 * c0; k < nn; k += 128)
+            *reinterpret_cast<f32x4 *>(dr + k) = *reinterpret_cast<const f32x4 *>(src + k);
+        } else {
+          for (int k = c0; k < nn; k += 32) dr[k] = src[k];
+        }
+      } else {
+        for (int k = c0; k < nn; k += 32) dr[k] = 0.0f;
+      }
     }
     wv.w = d;
     wv.ldw = wld;
   } else if constexpr (PREC == 2) {
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-      const int r = idx / nn, k = idx - r * nn;
-      lds[r * wld + k] = w.w64[(mbeg + r) * w.ldw + k];
+    for (int r = r0; r < 16 * MT; r += 8) {
+      double *dr = lds + r * wld;
+      if (r < rows) {
+        const double *src = w.w64 + (mbeg + r) * w.ldw;
+        for (int k = c0; k < nn; k += 32) dr[k] = src[k];
+      } else {
+        for (int k = c0; k < nn; k += 32) dr[k] = 0.0;
+      }
     }
     wv.w64 = lds;
     wv.ldw = wld;
   } else {
     __bf16 *h = reinterpret_cast<__bf16 *>(lds), *l = h + 16 * MT * wld;
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-      const int r = idx / nn, k = idx - r * nn;
-      h[r * wld + k] = w.w_hi[(mbeg + r) * w.ldw_bf + k];
-      l[r * wld + k] = w.w_lo[(mbeg + r) * w.ldw_bf + k];
+    for (int r = r0; r < 16 * MT; r += 8) {
+      __bf16 *hr = h + r * wld, *lr = l + r * wld;
+      if (r < rows) {
+        const __bf16 *sh = w.w_hi + (mbeg + r) * w.ldw_bf, *sl = w.w_lo + (mbeg + r) * w.ldw_bf;
+        for (int k = c0; k < nn; k += 32) {
+          hr[k] = sh[k];
+          lr[k] = sl[k];
+        }
+      } else {
+        for (int k = c0; k < nn; k += 32) {
+          hr[k] = (__bf16)0.0f;
+          lr[k] = (__bf16)0.0f;
+        }
+      }
     }
     wv.w_hi = h;
     wv.w_lo = l;
@@ -401,9 +431,10 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
   FiberW wv = w;
   int64_t pm0 = mbeg, pmend = mend;
   if constexpr (WL) {
+    // rows past mcount are zero in the copy: all 16 MT rows read as data
     stage_w<MT, PREC>(w, mbeg, mend, in.n, wld, lds_raw, wv);
     pm0 = 0;
-    pmend = mend - mbeg;
+    pmend = 16 * MT;
   }
   AccT<PREC> acc[MT][NT];
   double x2 = 0.0, e2 = 0.0;
@@ -432,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
         for (int nt = 0; nt < NT; ++nt) xc[nt] = xn[nt];
         if (jt + 1 < jtiles) ldx(jt + 1);
         AccT<PREC> racc[NT];
-        recon_tile<MT, NT, PREC>(wv, mcount, in.n, jt, acc, racc);
+        recon_tile<MT, NT, PREC>(wv, WL ? 16 * MT : mcount, in.n, jt, acc, racc);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           if (fib[nt] >= in.F) continue;
@@ -446,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
     }
     for (int jt = 0; jt < (fast ? 0 : jtiles); ++jt) {
       AccT<PREC> racc[NT];
-      recon_tile<MT, NT, PREC>(wv, mcount, in.n, jt, acc, racc);
+      recon_tile<MT, NT, PREC>(wv, WL ? 16 * MT : mcount, in.n, jt, acc, racc);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (fib[nt] >= in.F) continue;
