@@ -151,6 +151,7 @@ struct st_handle {
   DBuf<double> sd, sz, szh, smu, srot_cs, szz;
   DBuf<int> sact, sK, sdefl, sorg, srot_t, scounts;
   double *hpin = nullptr;  // pinned host scratch
+  double *hpin_dev = nullptr;  // device view of hpin (kernels publish results there)
   size_t hpin_cap = 0;
 
   // optional per-group timing with HIP events on `stream`
@@ -248,6 +249,7 @@ struct st_handle {
     hpin = nullptr;
     hpin_cap = 0;
     hipError_t e = hipHostMalloc((void **)&hpin, count * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&hpin_dev, hpin, 0);
     if (e == hipSuccess) hpin_cap = count;
     return e;
   }
@@ -581,8 +583,7 @@ int st_handle::do_update(const float *y) {
       x = Dspec[k].p;
       x64 = 1;
     }
-    e = hipMemcpyAsync(hpin, specsums.p, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost,
-                       stream);
+    e = launch_gather3(hpin_dev, specsums.p, 2 * m, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "residual norms");
     settle();
@@ -744,12 +745,7 @@ int st_handle::do_update(const float *y) {
   // 4 R r flops (two products with V^T) + 2 R r (row dots); V (FP64) read twice, d twice
   toc(ST_K_ISVD, 6.0 * Rnew * rdi, 2.0 * 8.0 * Rold * rdi + 2.0 * 8.0 * Rnew);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin, sums.p, sizeof(double), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 3, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 3 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
-                       stream);
+    e = launch_gather3(hpin_dev, sums.p, 1, 0, p.p, rdi, 3, p2.p, rdi, 3 + rdi, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "isvd projections");
   settle();
@@ -841,7 +837,7 @@ int st_handle::do_update(const float *y) {
   e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
   toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + 1.0) * c));
   if (e != hipSuccess) return hipfail(e, "streaming factor update");
-  e = hipMemcpyAsync(hpin, S[nxt].p, c * sizeof(double), hipMemcpyDeviceToHost, stream);
+  e = launch_gather3(hpin_dev, S[nxt].p, (int)c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "streaming update");
   settle();
@@ -929,12 +925,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   // V0 and d read once (FP64); r x r products
   toc(ST_K_ISVD, 2.0 * Rnew * rdi + 10.0 * (double)rdi * rdi, 8.0 * Rnew * (rdi + 1.0));
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 3, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hpin + 3 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
-                       stream);
+    e = launch_gather3(hpin_dev, sc, 3, 0, p.p, rdi, 3, p2.p, rdi, 3 + rdi, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "isvd projections");
   settle();
@@ -969,12 +960,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
                            nullptr, stream);
     toc(ST_K_ISVD, 4.0 * Rnew * rdi, 8.0 * Rnew * (rdi + 1.0));
     if (e == hipSuccess)
-      e = hipMemcpyAsync(hpin, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hpin + 3, p.p, rdi * sizeof(double), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hpin + 3 + rdi, p2.p, rdi * sizeof(double), hipMemcpyDeviceToHost,
-                         stream);
+      e = launch_gather3(hpin_dev, sc, 3, 0, p.p, rdi, 3, p2.p, rdi, 3 + rdi, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "exact second pass");
     settle();
@@ -1051,7 +1037,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
   toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + 1.0) * c));
   if (e != hipSuccess) return hipfail(e, "streaming factor update");
-  e = hipMemcpyAsync(hpin, S[nxt].p, c * sizeof(double), hipMemcpyDeviceToHost, stream);
+  e = launch_gather3(hpin_dev, S[nxt].p, (int)c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "streaming update");
   settle();

@@ -150,6 +150,26 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
   }
 }
 
+// dst[oa + i] = a[i] (i < na), dst[ob + i] = b[i] (i < nb), dst[oc + i] = c[i]
+// (i < nc): one launch that publishes small results, typically into pinned
+// host memory mapped for the device (no copy engine or blit per array).
+__global__ void gather3_kernel(double *dst, const double *a, int na, int oa, const double *b,
+                               int nb, int ob, const double *c, int nc, int oc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) dst[oa + i] = a[i];
+  else if (i < na + nb) dst[ob + i - na] = b[i - na];
+  else if (i < na + nb + nc) dst[oc + i - na - nb] = c[i - na - nb];
+}
+
+hipError_t launch_gather3(double *dst, const double *a, int na, int oa, const double *b, int nb,
+                          int ob, const double *c, int nc, int oc, hipStream_t s) {
+  const int n = na + nb + nc;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, a,
+                     na, oa, b, nb, ob, c, nc, oc);
+  return hipGetLastError();
+}
+
 // One block per column: out[j] = sum_b part[j * nb + b] (fixed tree order);
 // optionally out2[j] = out[j] + add[j]; block r (if q2part) sums q2part.
 __global__ __launch_bounds__(256) void colsum_kernel(const double *part, int nb, int r,

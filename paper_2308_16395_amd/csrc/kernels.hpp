@@ -20,6 +20,8 @@ struct IsvdArgs {
 };
 
 int isvd_blocks(int64_t R);
+hipError_t launch_gather3(double *dst, const double *a, int na, int oa, const double *b, int nb,
+                          int ob, const double *c, int nc, int oc, hipStream_t s);
 hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s);
 hipError_t launch_colsum(const double *part, int nb, int r, double *out, const double *add,
                          double *out2, const double *q2part, double *q2, hipStream_t s);
