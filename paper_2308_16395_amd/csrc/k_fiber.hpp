@@ -156,12 +156,63 @@ __device__ inline void load_wbf8(const __bf16 *wb, int64_t ld, int64_t m, int64_
   }
 }
 
+// Chunked W in LDS: rows [m0, m0 + 16 MT) x columns [c0, c0 + NC) of W, in the
+// form the product precision reads, copied into lds as [16 MT][LD] with rows
+// past mend and columns past K zero-filled (so readers need no bounds tests),
+// and a FiberW view of that chunk (rows and columns counted from its corner).
+template <int MT, int PREC, int NC, int LD>
+__device__ inline void wchunk_copy(const FiberW &w, int64_t m0, int64_t mend, int64_t K,
+                                   int64_t c0, double *lds, FiberW &view) {
+  constexpr int total = 16 * MT * NC;
+  for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+    const int r = idx / NC, c = idx % NC;  // NC is a power of two
+    const int64_t m = m0 + r, k = c0 + c;
+    const bool ok = m < mend && k < K;
+    if constexpr (PREC == 0) {
+      reinterpret_cast<float *>(lds)[r * LD + c] = load_or0(w.w, m * w.ldw + k, ok);
+    } else if constexpr (PREC == 2) {
+      lds[r * LD + c] = load_or0(w.w64, m * w.ldw + k, ok);
+    } else {
+      __bf16 *h = reinterpret_cast<__bf16 *>(lds);
+      h[r * LD + c] = load_or0(w.w_hi, m * w.ldw_bf + k, ok);
+      h[16 * MT * LD + r * LD + c] = load_or0(w.w_lo, m * w.ldw_bf + k, ok);
+    }
+  }
+  view = w;
+  if constexpr (PREC == 0) {
+    view.w = reinterpret_cast<float *>(lds);
+    view.ldw = LD;
+  } else if constexpr (PREC == 2) {
+    view.w64 = lds;
+    view.ldw = LD;
+  } else {
+    view.w_hi = reinterpret_cast<__bf16 *>(lds);
+    view.w_lo = view.w_hi + 16 * MT * LD;
+    view.ldw_bf = LD;
+  }
+}
+// row strides of the projection (32 columns) and reconstruction (16) chunks:
+// multiples of 4 floats / 8 bf16 for the vector reads, padded off the banks
+template <int PREC>
+constexpr int kChunkLdP = PREC == 0 ? 36 : (PREC == 2 ? 34 : 40);
+template <int PREC>
+constexpr int kChunkLdR = PREC == 0 ? 20 : (PREC == 2 ? 18 : 24);
+template <int MT, int PREC>
+constexpr size_t chunk_lds_bytes() {
+  constexpr size_t es = PREC == 2 ? 8 : 4;  // bf16: hi and lo
+  constexpr size_t p = (size_t)16 * MT * kChunkLdP<PREC> * es;
+  constexpr size_t r = (size_t)16 * MT * kChunkLdR<PREC> * es;
+  return p > r ? p : r;
+}
+
 // acc[mt][nt] = sum over K of W[m0+16mt.., k] X[fibres of nt, k]. Also sums the
 // squares of every X element this wave loads (each element is loaded once).
-template <int MT, int NT, bool CONTIG, int PREC, bool NORMX, class TIN>
+// WC: W is read from an LDS chunk of 32 columns staged per K block by the
+// whole block (`lds`); every wave of the block must call this together.
+template <int MT, int NT, bool CONTIG, int PREC, bool NORMX, class TIN, bool WC = false>
 __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t m0, int64_t mend,
                                     const int64_t (&base)[NT], AccT<PREC> (&acc)[MT][NT],
-                                    double &x2) {
+                                    double &x2, double *lds = nullptr) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
   const int64_t K = in.n;
@@ -214,6 +265,19 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
       for (int s = 0; s < 8; ++s)
         xv[nt][s] = ((xm >> (8 * nt + s)) & 1u) ? (OpT<PREC>)xr[nt][s] : (OpT<PREC>)0;
     if (PF && kb + 32 < K) fetch(kb + 32);
+    // the W source of this block: W itself, or its LDS chunk (corner at row m0,
+    // column kb; out-of-range entries zero)
+    FiberW wsrc = w;
+    int64_t wm0 = m0, wmend = mend, wk0 = k0, wK = K;
+    if constexpr (WC) {
+      __syncthreads();  // every wave is done with the previous chunk
+      wchunk_copy<MT, PREC, 32, kChunkLdP<PREC>>(w, m0, mend, K, kb, lds, wsrc);
+      __syncthreads();
+      wm0 = 0;
+      wmend = 16 * MT;
+      wk0 = 8 * grp;
+      wK = 32;
+    }
     if (NORMX) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
@@ -224,7 +288,7 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         float wv[8];
-        load_w8(w, m0 + 16 * mt + col, mend, K, k0, wv);
+        load_w8(wsrc, wm0 + 16 * mt + col, wmend, wK, wk0, wv);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
 #pragma unroll
@@ -234,7 +298,7 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         double wv[8];
-        load_w8_f64(w.w64, w.ldw, m0 + 16 * mt + col, mend, K, k0, wv);
+        load_w8_f64(wsrc.w64, wsrc.ldw, wm0 + 16 * mt + col, wmend, wK, wk0, wv);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
 #pragma unroll
@@ -247,9 +311,9 @@ __device__ inline void project_wave(const FiberIn &in, const FiberW &w, int64_t 
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         bf16x8 wh, wl;
-        const int64_t m = m0 + 16 * mt + col;
-        load_wbf8(w.w_hi, w.ldw_bf, m, mend, K, k0, wh);
-        load_wbf8(w.w_lo, w.ldw_bf, m, mend, K, k0, wl);
+        const int64_t m = wm0 + 16 * mt + col;
+        load_wbf8(wsrc.w_hi, wsrc.ldw_bf, m, wmend, wK, wk0, wh);
+        load_wbf8(wsrc.w_lo, wsrc.ldw_bf, m, wmend, wK, wk0, wl);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           acc[mt][nt] = mfma_bf(wh, xh[nt], acc[mt][nt]);
@@ -409,7 +473,8 @@ __host__ __device__ inline size_t w_lds_bytes(int wld) {
 // lane. With WL the block's rows of W are first copied into LDS (row stride
 // wld) and both products read them from there; the output tile then reuses
 // that LDS after the residual.
-template <int MT, int NT, bool CONTIG, bool RESID, int PREC, class TIN, class TOUT, bool WL>
+template <int MT, int NT, bool CONTIG, bool RESID, int PREC, class TIN, class TOUT, bool WL,
+          bool WC = false>
 __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, int m0, int mcount,
                                                          FiberOut out, double *partials,
                                                          int stage, int wld) {
@@ -438,7 +503,20 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
   }
   AccT<PREC> acc[MT][NT];
   double x2 = 0.0, e2 = 0.0;
-  project_wave<MT, NT, CONTIG, PREC, RESID, TIN>(in, wv, pm0, pmend, base, acc, x2);
+  project_wave<MT, NT, CONTIG, PREC, RESID, TIN, WC>(in, wv, pm0, pmend, base, acc, x2, lds_raw);
+  // WC: the reconstruction reads W[:, 16 jt .. 16 jt + 16) from an LDS chunk
+  // staged per tile (zero rows past mcount)
+  auto recon = [&](int jt, AccT<PREC> (&racc)[NT]) {
+    if constexpr (WC) {
+      FiberW wr;
+      __syncthreads();  // every wave is done with the previous chunk
+      wchunk_copy<MT, PREC, 16, kChunkLdR<PREC>>(w, 0, mcount, in.n, 16 * jt, lds_raw, wr);
+      __syncthreads();
+      recon_tile<MT, NT, PREC>(wr, 16 * MT, 16, 0, acc, racc);
+    } else {
+      recon_tile<MT, NT, PREC>(wv, WL ? 16 * MT : mcount, in.n, jt, acc, racc);
+    }
+  };
 
   if constexpr (RESID) {
     // (with RESID, m0 == 0 and the block holds all mcount rows of W)
@@ -463,7 +541,7 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
         for (int nt = 0; nt < NT; ++nt) xc[nt] = xn[nt];
         if (jt + 1 < jtiles) ldx(jt + 1);
         AccT<PREC> racc[NT];
-        recon_tile<MT, NT, PREC>(wv, WL ? 16 * MT : mcount, in.n, jt, acc, racc);
+        recon(jt, racc);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           if (fib[nt] >= in.F) continue;
@@ -477,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
     }
     for (int jt = 0; jt < (fast ? 0 : jtiles); ++jt) {
       AccT<PREC> racc[NT];
-      recon_tile<MT, NT, PREC>(wv, WL ? 16 * MT : mcount, in.n, jt, acc, racc);
+      recon(jt, racc);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (fib[nt] >= in.F) continue;
@@ -507,7 +585,7 @@ __global__ __launch_bounds__(kThreads) void fiber_kernel(FiberIn in, FiberW w, i
   }
 
   if (stage) {
-    if constexpr (WL) __syncthreads();  // every wave is done with the W copy
+    if constexpr (WL || WC) __syncthreads();  // every wave is done with the W copy
     constexpr int TW = 16 * MT;  // outputs per fibre in this block
     constexpr int TWP = TW + 1;  // padded LDS row (odd: spreads the banks)
     TOUT *tile = reinterpret_cast<TOUT *>(lds_raw) + (size_t)wid * (16 * NT) * TWP;
@@ -862,6 +940,18 @@ hipError_t launch_fiber_t(const FiberIn &in, const FiberW &w, int m0, int mcount
       hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT, true>), grid,
                          dim3(kThreads), wb > slds ? wb : slds, s, in, w, m0, mcount, out,
                          partials, stage, wld);
+      if (nparts) *nparts = (int)grid.x;
+      return hipGetLastError();
+    }
+    // too large for one copy: the split-bf16 form stages W (hi and lo) through
+    // LDS in chunks shared by the block's four waves (measured on the
+    // 512x512x256 stream: mode-1 TTM 0.57 -> 0.40 ms). The FP32 form keeps its
+    // direct 16-byte reads of W, which measured faster than the chunk copies.
+    constexpr size_t cb = chunk_lds_bytes<MT, PREC>();
+    if (PREC == 1 && cb <= 64 * 1024) {
+      hipLaunchKernelGGL((fiber_kernel<MT, NT, CONTIG, RESID, PREC, TIN, TOUT, false, true>), grid,
+                         dim3(kThreads), cb > slds ? cb : slds, s, in, w, m0, mcount, out,
+                         partials, stage, 0);
       if (nparts) *nparts = (int)grid.x;
       return hipGetLastError();
     }
