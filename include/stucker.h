@@ -19,7 +19,8 @@
  *    caller keeps ownership and the library does not retain them.
  *  - Calls are synchronous with respect to the host: when a call returns, its
  *    device work on the handle's stream has finished and the inputs may be
- *    reused. A handle must not be used from two threads at once.
+ *    reused. The one exception is st_update (see there). A handle must not be
+ *    used from two threads at once.
  *  - Streams: a `stream` argument is a hipStream_t of the HIP runtime this
  *    library links (libamdhip64.so.7), or NULL for that runtime's null stream.
  *    A process may hold a second HIP runtime (for example one bundled with a
@@ -158,7 +159,14 @@ int st_init(st_handle *h, const float *x0, int64_t n_init);
  * n_1 x ... x n_{d-1}. Runs Alg. 4 for modes 1..d-1, then Alg. 3 on the
  * streaming mode and the core update. Errors: ST_ESTATE (not initialised),
  * ST_ENONFINITE, ST_ECAPACITY, ST_ESOLVER, ST_ENOMEM, ST_EHIP; in every error
- * case the decomposition is unchanged. */
+ * case the decomposition is unchanged. The call returns once the update is
+ * committed (ranks, counters); the tail of its device work (the rotations and
+ * the factor update) may still run on the handle's stream, so the next update
+ * queues behind it without an idle gap. Every later call on the handle orders
+ * after it; y may be reused once that stream has reached this point (any later
+ * synchronising call, or a stream synchronisation). The new singular values
+ * are checked when they are next read (the next st_update or st_sv): a
+ * non-positive value is reported there as ST_ESOLVER. */
 int st_update(st_handle *h, const float *y);
 
 /* Current ranks r_1..r_d (ranks[0..d-1]) and the number of slices n_d seen. */

@@ -10,9 +10,13 @@ torch here carries its own copy of the HIP runtime with the same soname as the
 system one the library links. Importing torch first makes the dynamic loader
 bind the library to that already-loaded copy, so one runtime serves both; the
 module refuses to load if two copies end up mapped (they would each claim the
-GPU). Every wrapper still finishes torch's queued work first (``_ready``) and
-runs the library on the runtime's null stream (or on a raw stream handle passed
-as an int); library calls return after their device work has finished.
+GPU). The library runs on the runtime's null stream (or on a raw stream handle
+passed as an int), which is also torch's default stream, so torch work queued
+there is ordered before each call; ``_ready`` waits only for work on another
+torch stream. Library calls that hand results to the caller return after their
+device work has finished; ``st_update`` may return while the tail of its device
+work still runs on the library's stream (later calls and torch's default stream
+order after it).
 """
 
 from __future__ import annotations
@@ -169,11 +173,16 @@ st_last_error = lib.st_last_error
 
 
 def _ready():
-    """Finish torch's queued device work before a library call reads or writes
-    torch-allocated memory."""
+    """Order torch's queued device work before a library call that reads or
+    writes torch-allocated memory. The library runs on the runtime's null
+    stream: work torch queued on its default stream (the same null stream) is
+    already ordered before it, so only work on another torch stream is waited
+    for here."""
     import torch
 
-    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    if cur.cuda_stream != 0:
+        cur.synchronize()
 
 
 def _stream_arg(stream):

@@ -152,6 +152,11 @@ struct st_handle {
   DBuf<int> sact, sK, sdefl, sorg, srot_t, scounts;
   double *hpin = nullptr;  // pinned host scratch
   double *hpin_dev = nullptr;  // device view of hpin (kernels publish results there)
+  // Singular values of the last update, published to pinned memory (hS) without
+  // a synchronisation; taken into S_host by finish_pending() after the next one.
+  double *hS = nullptr, *hS_dev = nullptr;
+  size_t hS_cap = 0;
+  int64_t s_pending = 0;
   size_t hpin_cap = 0;
 
   // optional per-group timing with HIP events on `stream`
@@ -243,9 +248,35 @@ struct st_handle {
     return p_;
   }
 
+  // (only while no publication into hS is pending)
+  hipError_t ensure_hS(size_t count) {
+    if (count <= hS_cap) return hipSuccess;
+    if (hS) (void)hipHostFree(hS);
+    hS = hS_dev = nullptr;
+    hS_cap = 0;
+    const size_t want = std::max<size_t>(count, 2 * count + 64);
+    hipError_t e = hipHostMalloc((void **)&hS, want * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&hS_dev, hS, 0);
+    if (e == hipSuccess) hS_cap = want;
+    return e;
+  }
+  // After a stream synchronisation: take the last update's singular values.
+  int finish_pending() {
+    if (!s_pending) return ST_OK;
+    const int64_t c = s_pending;
+    s_pending = 0;
+    for (int64_t i = 0; i < c; ++i)
+      if (!std::isfinite(hS[i]) || hS[i] <= 0.0)
+        return fail(ST_ESOLVER, "small SVD produced a non-positive singular value");
+    S_host.assign(hS, hS + c);
+    return ST_OK;
+  }
+
   hipError_t ensure_pinned(size_t count) {
     if (count <= hpin_cap) return hipSuccess;
-    if (hpin) (void)hipHostFree(hpin);
+    (void)hipStreamSynchronize(stream);  // pending work may still write hS
+  if (hpin) (void)hipHostFree(hpin);
+  if (hS) (void)hipHostFree(hS);
     hpin = nullptr;
     hpin_cap = 0;
     hipError_t e = hipHostMalloc((void **)&hpin, count * sizeof(double), hipHostMallocDefault);
@@ -587,6 +618,8 @@ int st_handle::do_update(const float *y) {
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "residual norms");
     settle();
+    rc = finish_pending();
+    if (rc != ST_OK) return rc;
     ynorm2 = hpin[1];
     if (!std::isfinite(ynorm2)) return fail(ST_ENONFINITE, "slice is not finite");
     eps = tau * std::sqrt(ynorm2 / d);
@@ -694,8 +727,8 @@ int st_handle::do_update(const float *y) {
     int64_t cf = 0;
     rc = stream_factored(map, dvec, Rold, Rnew, eps, stt, growf, q2f, cf, v0next);
     if (rc != ST_OK) return rc;
-    // ---- commit ----
-    S_host.assign(hpin, hpin + cf);
+    // ---- commit (the singular values follow through hS) ----
+    s_pending = cf;
     for (int k = 0; k < m; ++k) r[k] = rn[k];
     rd = cf;
     nd += 1;
@@ -837,16 +870,17 @@ int st_handle::do_update(const float *y) {
   e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
   toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + 1.0) * c));
   if (e != hipSuccess) return hipfail(e, "streaming factor update");
-  e = launch_gather3(hpin_dev, S[nxt].p, (int)c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  // The new singular values go to pinned memory without a synchronisation: the
+  // device work of this update may still run when the call returns, and the
+  // next call that needs them (the next update's first synchronisation, st_sv)
+  // takes them (finish_pending).
+  e = ensure_hS((size_t)c);
+  if (e == hipSuccess)
+    e = launch_gather3(hS_dev, S[nxt].p, (int)c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
   if (e != hipSuccess) return hipfail(e, "streaming update");
-  settle();
-  for (int64_t i = 0; i < c; ++i)
-    if (!std::isfinite(hpin[i]) || hpin[i] <= 0.0)
-      return fail(ST_ESOLVER, "small SVD produced a non-positive singular value");
 
   // ---- commit ----
-  S_host.assign(hpin, hpin + c);
+  s_pending = c;
   for (int k = 0; k < m; ++k) r[k] = rn[k];
   rd = c;
   nd += 1;
@@ -1037,13 +1071,11 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   e = launch_ud_update(Ud[cur].p, ud_ld[cur], nd, rdi, U2.p, (int)c, Ud[nxt].p, ldn, stream);
   toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + 1.0) * c));
   if (e != hipSuccess) return hipfail(e, "streaming factor update");
-  e = launch_gather3(hpin_dev, S[nxt].p, (int)c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  // published without a synchronisation, as in the literal form
+  e = ensure_hS((size_t)c);
+  if (e == hipSuccess)
+    e = launch_gather3(hS_dev, S[nxt].p, (int)c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
   if (e != hipSuccess) return hipfail(e, "streaming update");
-  settle();
-  for (int64_t i = 0; i < c; ++i)
-    if (!std::isfinite(hpin[i]) || hpin[i] <= 0.0)
-      return fail(ST_ESOLVER, "small SVD produced a non-positive singular value");
   v0next = w0;
   return ST_OK;
 }
@@ -1393,8 +1425,16 @@ int st_factor(const st_handle *hc, int mode, double *out, int64_t cap, int64_t *
   return ST_OK;
 }
 
-int st_sv(const st_handle *h, double *s, int64_t cap, int64_t *count) {
-  if (!h) return ST_EINVAL;
+int st_sv(const st_handle *hc, double *s, int64_t cap, int64_t *count) {
+  if (!hc) return ST_EINVAL;
+  st_handle *h = const_cast<st_handle *>(hc);  // takes a pending publication
+  if (h->s_pending) {
+    const hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hipfail(e, "singular values");
+    h->settle();
+    const int rc = h->finish_pending();
+    if (rc != ST_OK) return rc;
+  }
   if (count) *count = (int64_t)h->S_host.size();
   if (!s) return ST_OK;
   if (cap < (int64_t)h->S_host.size()) return ST_ESMALL;
@@ -1534,6 +1574,8 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
 
 int st_profile(st_handle *h, st_kernel_profile *out, int32_t count, int32_t reset) {
   if (!h || (out == nullptr && count > 0) || count < 0) return ST_EINVAL;
+  // the last update's device work may still be running: fold its intervals in
+  if (hipStreamSynchronize(h->stream) == hipSuccess) h->settle();
   for (int i = 0; i < count && i < ST_K_GROUPS; ++i) out[i] = h->prof[i];
   if (reset)
     for (int i = 0; i < ST_K_GROUPS; ++i) h->prof[i] = st_kernel_profile{};
