@@ -163,8 +163,8 @@ int st_init(st_handle *h, const float *x0, int64_t n_init);
  * committed (ranks, counters); the tail of its device work (the rotations and
  * the factor update) may still run on the handle's stream, so the next update
  * queues behind it without an idle gap. Every later call on the handle orders
- * after it; y may be reused once that stream has reached this point (any later
- * synchronising call, or a stream synchronisation). The new singular values
+ * after it. y is read only before the first internal synchronisation, so it
+ * may be reused when the call returns. The new singular values
  * are checked when they are next read (the next st_update or st_sv): a
  * non-positive value is reported there as ST_ESOLVER. */
 int st_update(st_handle *h, const float *y);
