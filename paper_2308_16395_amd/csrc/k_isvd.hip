@@ -273,6 +273,9 @@ __global__ __launch_bounds__(256) void sec_prep_kernel(SecData s, const double *
   __shared__ int wcount[2][4];
   __shared__ double red[16];
   const int r = s.r, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // zhat is scattered by sec_zhat_kernel into a zeroed array (deflated entries
+  // stay zero); clear it here rather than in a launch of its own
+  for (int t = tid; t < s.n; t += blockDim.x) s.zh[t] = 0.0;
   for (int t = tid; t <= r; t += blockDim.x) {
     if (t == 0) {
       s.d[0] = 0.0;
@@ -373,11 +376,6 @@ __global__ __launch_bounds__(256) void sec_zhat_kernel(SecData s) {
   if (lane == 0) s.zh[s.K[jt]] = z;
 }
 
-__global__ void sec_zero_zh_kernel(SecData s) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < s.n) s.zh[t] = 0.0;
-}
-
 // One wave (block of 64) per output triplet. U2 and V2 are (r+1) x ntrip,
 // column-major with leading dimension r+1, in the original index order of S'.
 __global__ __launch_bounds__(64) void sec_vec_kernel(SecData s, int ntrip, double *U2, double *V2,
@@ -404,7 +402,6 @@ hipError_t launch_secular_svd(SecData s, const double *S, const double *p, doubl
                               double tol, int ntrip, double *U2, double *V2, double *Snew,
                               hipStream_t st) {
   const int n = s.n;
-  hipLaunchKernelGGL(sec_zero_zh_kernel, dim3((n + 255) / 256), dim3(256), 0, st, s);
   hipLaunchKernelGGL(sec_prep_kernel, dim3(1), dim3(256), 0, st, s, S, p, q, grow, tol);
   hipLaunchKernelGGL(sec_roots_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   hipLaunchKernelGGL(sec_zhat_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
