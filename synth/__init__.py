@@ -16,6 +16,8 @@ from .generators import (  # noqa: F401
     BlobStream,
     FourierStream,
     SineWaveTensor,
+    SineWaveStream,
+    SINE_WAVE,
     make_stream,
     CONFIGS,
 )

@@ -197,6 +197,84 @@ class SineWaveTensor:
         return tuple(2 * f + 1 for f in self.freqs)
 
 
+class SineWaveStream:
+    """Noisy sine-wave stream with a rank bump (paper section 5.1, Fig. 3, Table 1).
+
+    Two blocks of ``n_half`` slices sampled from
+    f(x) = sum_j c_j sin(pi (j_1 x_1 + ... + j_d x_d)) on [-1, 1]^d (grid end
+    points included, c_j i.i.d. N(0, 1)); the streaming coordinate x_d runs over
+    its own uniform grid in each block. The first block keeps the terms with
+    |j_d| <= f_a, the second all terms up to |j_d| <= f_b, with the same
+    coefficients for the shared j, so the streaming-mode rank is 2 f_a + 1 over
+    the first block and 2 f_b + 1 over the whole stream, and the spatial ranks
+    are 2 f_k + 1 throughout. Gaussian noise, one seeded generator per slice, is
+    scaled so that its norm over the whole stream is ``eta`` times that of the
+    noise-free stream.
+
+    The sum is evaluated in separable form: for each j_d the complex spatial
+    field B_{j_d} = sum_{j_1..j_{d-1}} c_j prod_k exp(i pi j_k x_k), and a slice
+    at coordinate s is Im(sum_{j_d} B_{j_d} exp(i pi j_d s)), which equals the
+    sum of sines term by term.
+    """
+
+    def __init__(self, dims=(100, 100), n_half=2500, freqs=(5, 5), f_a=5, f_b=7,
+                 eta=1e-3, seed=1005):
+        self.dims = tuple(int(n) for n in dims)
+        self.freqs = tuple(int(f) for f in freqs)
+        self.n_half = int(n_half)
+        self.n_slices = 2 * self.n_half
+        self.f_a, self.f_b = int(f_a), int(f_b)
+        self.eta = float(eta)
+        self.seed = int(seed)
+        rng = np.random.default_rng(seed)
+        coef = rng.standard_normal(tuple(2 * f + 1 for f in self.freqs) + (2 * self.f_b + 1,))
+        field = coef.astype(np.complex128)
+        for ax, (n, f) in enumerate(zip(self.dims, self.freqs)):
+            x = np.linspace(-1.0, 1.0, n)
+            e = np.exp(1j * np.pi * np.outer(x, np.arange(-f, f + 1)))  # n x (2f+1)
+            field = np.moveaxis(np.tensordot(e, field, axes=([1], [ax])), 0, ax)
+        # columns: j_d = -f_b .. f_b; rows: the slice in column-major order
+        self._basis = field.reshape(-1, 2 * self.f_b + 1, order="F")
+        self._jd = np.arange(-self.f_b, self.f_b + 1)
+        self._grid = np.linspace(-1.0, 1.0, self.n_half)
+        sig2 = 0.0
+        noise2 = 0.0
+        for t in range(self.n_slices):
+            sig2 += float(np.sum(self._clean(t) ** 2))
+            noise2 += float(np.sum(self._noise_raw(t) ** 2))
+        self.clean_norm = math.sqrt(sig2)
+        self._noise_scale = self.eta * self.clean_norm / math.sqrt(noise2)
+
+    def _clean(self, t):
+        blk, i = divmod(int(t), self.n_half)
+        keep = np.abs(self._jd) <= (self.f_a if blk == 0 else self.f_b)
+        w = np.exp(1j * np.pi * self._jd[keep] * self._grid[i])
+        return (self._basis[:, keep] @ w).imag
+
+    def _noise_raw(self, t):
+        return np.random.default_rng([self.seed, int(t)]).standard_normal(int(np.prod(self.dims)))
+
+    def slice_flat(self, t):
+        return self._clean(t) + self._noise_scale * self._noise_raw(t)
+
+    def slice(self, t):
+        return self.slice_flat(t).reshape(self.dims, order="F")
+
+    def slice_torch(self, t, device, dtype):
+        import torch
+        return torch.from_numpy(self.slice_flat(t)).to(device=device, dtype=dtype)
+
+    def expected_ranks(self):
+        """Exact ranks of the noise-free stream: spatial, then the streaming mode
+        over the first block and over the whole stream."""
+        return tuple(2 * f + 1 for f in self.freqs), 2 * self.f_a + 1, 2 * self.f_b + 1
+
+
+# The sine-wave experiment of paper section 5.1 (100 x 100 x 5000, rank bump at
+# slice 2500, eta = 1e-3, tau = 1e-2, initial ST-HOSVD on 200 slices).
+SINE_WAVE = dict(kind="sine", dims=(100, 100), n_half=2500, freqs=(5, 5), f_a=5, f_b=7,
+                 eta=1e-3, eps=1e-2, n_init=200, seed=1005)
+
 # The five workloads the benchmark and the parity tests use (0-indexed).
 CONFIGS = {
     0: dict(kind="lowrank", dims=(32, 32), n_slices=100, ranks=(4, 4, 6),
@@ -227,6 +305,9 @@ def make_stream(cfg, **overrides):
                           width=c.get("width", (4.0, 16.0)),
                           speed=c.get("speed", 0.5), n_slices=c["n_slices"],
                           seed=c["seed"])
+    if kind == "sine":
+        return SineWaveStream(dims=c["dims"], n_half=c["n_half"], freqs=c["freqs"],
+                              f_a=c["f_a"], f_b=c["f_b"], eta=c["eta"], seed=c["seed"])
     if kind == "fourier":
         return FourierStream(dims=c["dims"], n_modes=c.get("n_modes", 4096),
                              kmax=c.get("kmax", 64.0), drift=c.get("drift", 0.02),
