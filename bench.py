@@ -143,6 +143,54 @@ def large_bench(n_init=20, warmup=3, steps=30):
     return out
 
 
+def sine_bench():
+    """The sine-wave experiment of Sec. 5.1 (100 x 100 x 5000, rank bump at slice
+    2500, eta 1e-3, tau 1e-2): the streaming path (initial ST-HOSVD on 200
+    slices, then 4800 updates, FP32 products, literal core update) and the batch
+    ST-HOSVD of all 5000 slices at once, slices resident in HBM, whole-run wall
+    times."""
+    import numpy as np
+    import torch
+
+    import paper_2308_16395_amd as pkg
+    from synth import SINE_WAVE, make_stream
+
+    s = make_stream(SINE_WAVE)
+    tau, n_init, n = SINE_WAVE["eps"], SINE_WAVE["n_init"], s.n_slices
+    data = torch.from_numpy(
+        np.stack([s.slice_flat(t).astype(np.float32) for t in range(n)])).cuda()
+    out = dict(workload="sine wave 100x100x5000 (ranks (11,11,11) then (11,11,15)), "
+                        "eta 1e-3, tau 1e-2, FP32")
+    st = pkg.StreamingTucker(s.dims, tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.init(data[:n_init].reshape(-1), n_init)
+    r3 = {}
+    for t in range(n_init, n):
+        st.update(data[t])
+        if t in (s.n_half - 1, s.n_half):
+            r3[t] = st.ranks[2]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["stream"] = dict(seconds=round(dt, 3), slices_per_s=round((n - n_init) / dt, 1),
+                         ranks=list(st.ranks), recon_error_bound=st.recon_error()[0],
+                         r3_before_after_bump=[r3[s.n_half - 1], r3[s.n_half]])
+    st.close()
+    st = pkg.StreamingTucker(s.dims, tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.init(data.reshape(-1), n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["batch"] = dict(seconds=round(dt, 3), ranks=list(st.ranks),
+                        recon_error_bound=st.recon_error()[0])
+    st.close()
+    log(f"sine wave: {out}")
+    del data
+    torch.cuda.empty_cache()
+    return out
+
+
 def grad_bench(reps=5):
     """Reconstruct / Project forward and VJPs at GRAD_DIMS, FP32 products."""
     import numpy as np
@@ -228,6 +276,8 @@ def main():
                     help="skip the Reconstruct/Project forward and VJP timings")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the FP32 vs bf16x3 comparison on the 512x512x256 stream")
+    ap.add_argument("--no-sine", action="store_true",
+                    help="skip the sine-wave stream and batch run (100x100x5000)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size "
                          "kernel against which HBM byte counters are calibrated)")
@@ -369,6 +419,9 @@ def main():
     if not args.no_large:
         log("FP32 vs bf16x3 on the 512x512x256 stream")
         result["large_stream"] = large_bench()
+    if not args.no_sine:
+        log("sine-wave stream and batch ST-HOSVD (100x100x5000)")
+        result["sine_wave"] = sine_bench()
     if not args.no_grad:
         log("timing Reconstruct/Project forward and VJPs")
         result["differentiation"] = grad_bench()
