@@ -37,10 +37,14 @@ def compile_flags():
     ]
 
 
-# Per-source code generation options. The rotations keep their MFMA
-# accumulators in VGPRs: with the default AGPR form the compiler copies the
-# loop-carried accumulators between the two register files on every K block.
-SOURCE_FLAGS = {"k_rot.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-source code generation options. The rotations and the fibre kernels keep
+# their MFMA accumulators in VGPRs: with the default AGPR form the compiler
+# copies the loop-carried accumulators between the two register files on every
+# K block. (The Gram kernels keep the default: this compiler crashes on
+# k_gram.hip with the VGPR form.)
+_VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+SOURCE_FLAGS = {src: _VGPR_FORM for src in
+                ("k_rot.hip", "k_fiber_ff.hip", "k_fiber_fd.hip", "k_fiber_dd.hip")}
 
 
 def _compile(src):
