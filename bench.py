@@ -278,6 +278,9 @@ def main():
                     help="skip the FP32 vs bf16x3 comparison on the 512x512x256 stream")
     ap.add_argument("--no-sine", action="store_true",
                     help="skip the sine-wave stream and batch run (100x100x5000)")
+    ap.add_argument("--sine-only", action="store_true",
+                    help="run only the sine-wave stream and batch run and print their "
+                         "JSON (for profiling that workload alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size "
                          "kernel against which HBM byte counters are calibrated)")
@@ -287,6 +290,9 @@ def main():
               "stream and this build measures one GPU's share (see DESIGN.md on sharding).",
               file=sys.stderr)
         sys.exit(2)
+    if args.sine_only:
+        print(json.dumps(dict(sine_wave=sine_bench())), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -474,23 +474,35 @@ hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, 
 // the columns of small singular value would carry a relative error of about
 // u s_1 / s_k and V would not be orthonormal to the accuracy the ISVD residual
 // test needs.
-__global__ void init_vc_kernel(const double *A, int64_t R, int64_t nd, const double *Ud,
-                               int64_t ldu, int rd, const double *S, double *V, float *Cc) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= R) return;
-  for (int m = 0; m < rd; ++m) {
-    double acc = 0.0;
-    for (int64_t j = 0; j < nd; ++j) acc += A[row + R * j] * Ud[j + ldu * m];
-    if (Cc) Cc[row + R * m] = (float)acc;
-    V[row + R * m] = acc / S[m];
+// Block (x, m) covers rows 64 x .. 64 x + 63 of column m; its four waves take
+// every fourth slice j and their partial sums are added in a fixed order, so a
+// long initial batch (large nd) does not run as one serial loop per row.
+__global__ __launch_bounds__(256) void init_vc_kernel(const double *A, int64_t R, int64_t nd,
+                                                      const double *Ud, int64_t ldu, int rd,
+                                                      const double *S, double *V, float *Cc) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 64 + lane;
+  const int m = blockIdx.y;
+  double acc = 0.0;
+  if (row < R)
+    for (int64_t j = w; j < nd; j += 4) acc += A[row + R * j] * Ud[j + ldu * m];
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && row < R) {
+    const double t = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (Cc) Cc[row + R * m] = (float)t;
+    V[row + R * m] = t / S[m];
   }
 }
 
 hipError_t launch_init_vc(const double *A, int64_t R, int64_t nd, const double *Ud,
                           int64_t ldu, int rd, const double *S, double *V, float *Cc,
                           hipStream_t s) {
-  hipLaunchKernelGGL(init_vc_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, A, R, nd,
-                     Ud, ldu, rd, S, V, Cc);
+  if (R <= 0 || rd <= 0) return hipSuccess;
+  if (rd > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(init_vc_kernel, dim3((unsigned)((R + 63) / 64), (unsigned)rd), dim3(256), 0,
+                     s, A, R, nd, Ud, ldu, rd, S, V, Cc);
   return hipGetLastError();
 }
 
