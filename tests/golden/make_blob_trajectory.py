@@ -6,6 +6,12 @@ values the GPU library consumes), tau = 1e-4. Records after every slice the
 ranks, eps, ||E_k||/eps per slice mode, q/eps, and the branch taken, so the GPU
 run at full size can be compared decision by decision.
 
+At checkpoints (every 50 updates and after the last slice) it also records the
+oracle's reconstruction of probe slices {0, T//2, T} (T = the last slice seen)
+at a fixed seeded sample of element positions, together with the data values
+there, so a GPU run can be compared with the oracle element by element on
+reconstructed slices (sampled outputs; the full slices would be 268 MB each).
+
 Usage: python tests/golden/make_blob_trajectory.py [n_slices]
 """
 
@@ -20,24 +26,40 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-from oracle import StreamingTucker  # noqa: E402
+from oracle import StreamingTucker, vec  # noqa: E402
 from synth import make_stream  # noqa: E402
+
+N_SAMPLES = 1024
+SAMPLE_SEED = 2024
+
+
+def sample_positions(ny, n=N_SAMPLES, seed=SAMPLE_SEED):
+    """Sorted distinct flat (column-major) element indices of a slice."""
+    rng = np.random.default_rng(seed)
+    return np.unique(rng.integers(0, ny, size=n)).astype(np.int64)
 
 
 def main():
     n_slices = int(sys.argv[1]) if len(sys.argv) > 1 else 400
     s = make_stream(1)
     n_init, tau = 20, 1e-4
+    ny = int(np.prod(s.dims))
+    pos = sample_positions(ny)
+
+    def flat32(t):
+        return s.slice_flat(t).astype(np.float32).astype(np.float64)
 
     def sl(t):
-        return s.slice_flat(t).astype(np.float32).astype(np.float64).reshape(s.dims, order="F")
+        return flat32(t).reshape(s.dims, order="F")
 
     orc = StreamingTucker(np.stack([sl(t) for t in range(n_init)], axis=-1), tau)
     out = dict(
         source="FP64 oracle (oracle/tucker.py), blob stream config 1, float32 slice values",
         stream=dict(space=list(s.space), n_vars=s.n_vars, n_blobs=s.n_blobs, seed=1001,
                     n_init=n_init, tau=tau, n_slices=n_slices),
-        init_ranks=list(orc.ranks), init_bound=orc.recon_error_bound(), slices=[])
+        init_ranks=list(orc.ranks), init_bound=orc.recon_error_bound(), slices=[],
+        probe_positions=pos.tolist(), probe_sample_seed=SAMPLE_SEED, checkpoints=[])
+    checkpoints = set(range(n_init + 49, n_slices, 50)) | {n_slices - 1}
     t0 = time.time()
     for t in range(n_init, n_slices):
         rec = orc.update(sl(t))
@@ -46,6 +68,14 @@ def main():
             e_over_eps=[e / rec["eps"] for e in rec["e_norm"]], q_over_eps=rec["q"] / rec["eps"],
             grew=[int(g) for g in rec["r_new"]], ignored=bool(rec["ignored"]),
             bound=orc.recon_error_bound()))
+        if t in checkpoints:
+            probes = []
+            for tp in sorted({0, t // 2, t}):
+                rec_t = vec(orc.reconstruct_slice(tp))
+                probes.append(dict(t=tp, recon=rec_t[pos].tolist(),
+                                   data=flat32(tp)[pos].tolist(),
+                                   slice_norm=float(np.linalg.norm(flat32(tp)))))
+            out["checkpoints"].append(dict(after=t, probes=probes))
         print(t, orc.ranks, f"{time.time() - t0:.0f}s", flush=True)
     with open(os.path.join(HERE, "blobs128_oracle_trajectory.json"), "w") as f:
         json.dump(out, f)

@@ -211,3 +211,89 @@ def test_invalid_inputs_raise():
     with pytest.raises(ValueError):
         st.update(np.zeros((5, 6)))
     assert st.U[-1].shape[0] == 4
+
+
+def _threshold_case(level, alpha=0.1, n=8, tau=0.1):
+    """Old data: two rank-one slices of norm alpha (ranks (2, 2, 2), no
+    truncation). New slice: a part inside the old span plus three orthogonal
+    parts of norm level * tau * ||Y|| each, one outside the mode-1 span, one
+    outside the mode-2 span, and one inside both spans but outside the span of
+    the streaming-mode auxiliary matrix V (core coordinate (1, 2))."""
+    q_, _ = np.linalg.qr(np.random.default_rng(31).standard_normal((n, 3)))
+    a1, a2, a3 = q_.T
+    q_, _ = np.linalg.qr(np.random.default_rng(32).standard_normal((n, 3)))
+    b1, b2, b3 = q_.T
+    x0 = np.stack([alpha * np.outer(a1, b1), alpha * np.outer(a2, b2)], axis=-1)
+    g = level * tau
+    mu = math.sqrt(1.0 - 3.0 * g * g)  # ||Y|| = 1
+    y = (mu * np.outer(a1, b1) + g * np.outer(a1, b2) + g * np.outer(a3, b1)
+         + g * np.outer(a1, b3))
+    return x0, y, tau
+
+
+@pytest.mark.parametrize("level", [0.60, 0.80])
+def test_alg5_tolerance_splits_the_slice_budget_over_d(level):
+    """Alg. 5 gives every one of the d steps of a slice the tolerance
+    eps = tau ||Y|| / sqrt(d), so the d squared errors sum to at most
+    tau^2 ||Y||^2 (App. D). Residuals of level * tau ||Y|| with
+    1/sqrt(3) < level must therefore grow both slice modes and the streaming
+    rank, and the guarantee ||X - X^|| <= tau ||X|| holds after the slice. A
+    tolerance of tau ||Y|| (or tau ||Y|| / sqrt(d - 1) at level 0.6) would keep
+    all three parts and break the guarantee: the three squared residuals add
+    up to 3 level^2 tau^2 ||Y||^2 > tau^2 (||Y||^2 + ||X_old||^2)."""
+    x0, y, tau = _threshold_case(level)
+    st = StreamingTucker(x0, tau)
+    assert st.ranks == (2, 2, 2) and st.disc < 1e-14
+    rec = st.update(y)
+    assert rec["grew"] == [True, True]
+    assert not rec["ignored"]
+    assert st.ranks == (3, 3, 3)
+    x = np.concatenate([x0, y[..., None]], axis=-1)
+    err = np.linalg.norm(x - st.reconstruct())
+    assert err <= tau * np.linalg.norm(x)
+    # the three parts lie inside the grown spans: nothing is lost
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("core_update", ["literal", "factored"])
+def test_alg5_tolerance_keeps_residuals_below_tau_over_sqrt_d(core_update):
+    """The converse side of the same tolerance: residuals of 0.55 tau ||Y||
+    (below tau ||Y|| / sqrt(3) = 0.577 tau ||Y||) grow nothing, and the slice
+    adds the three squared residuals to the error bound (Prop. 3 for the slice
+    modes, Prop. 1 for the ignored ISVD residual). With the core kept as
+    C = V x_d S the error equals that bound (Prop. 1 is an equality); the
+    literal core update of Alg. 5 keeps part of the ignored residual, so its
+    error is at most the bound. A smaller tolerance such as tau ||Y|| / d would
+    grow all three."""
+    x0, y, tau = _threshold_case(0.55)
+    st = StreamingTucker(x0, tau, core_update=core_update)
+    rec = st.update(y)
+    assert rec["grew"] == [False, False] and rec["ignored"]
+    assert st.ranks == (2, 2, 2)
+    x = np.concatenate([x0, y[..., None]], axis=-1)
+    err = np.linalg.norm(x - st.reconstruct())
+    bound = st.recon_error_bound() * math.sqrt(st.xnorm2)
+    assert bound == pytest.approx(math.sqrt(3.0) * 0.55 * tau, rel=1e-9)
+    if core_update == "factored":
+        assert err == pytest.approx(bound, rel=1e-9)
+    else:
+        # the two slice-mode residuals are lost in any case
+        assert math.sqrt(2.0) * 0.55 * tau * (1 - 1e-9) <= err <= bound * (1 + 1e-12)
+    assert err <= tau * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("core_update", ["literal", "factored"])
+def test_reconstruct_slice_is_a_slice_of_the_reconstruction(core_update):
+    """reconstruct_slice(t) is slice t of C x_1 U_1 ... x_d U_d (Sec. 2.2) for
+    every t, initial and streamed slices alike."""
+    x = _lowrank_stream((7, 6, 5, 18), (3, 2, 2, 5), 41, 1e-2)
+    st = StreamingTucker(x[..., :4], 5e-2, core_update=core_update)
+    for t in range(4, x.shape[-1]):
+        st.update(x[..., t])
+    full = st.reconstruct()
+    assert full.shape == x.shape
+    for t in range(x.shape[-1]):
+        np.testing.assert_allclose(st.reconstruct_slice(t), full[..., t], rtol=0, atol=1e-13)
+    # and the slices differ from each other (a reversed or shifted row of U_d
+    # would be caught)
+    assert np.linalg.norm(full[..., 0] - full[..., -1]) > 1e-3
