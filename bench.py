@@ -4,7 +4,9 @@ Workload: the advecting-blob stream with 128 x 128 x 128 spatial slices and 16
 variables (4-way slices, d = 5), 400 slices, tau = 1e-4, initial ST-HOSVD on
 the first 20 slices. A step is one streaming update (Alg. 5) of one slice. All
 slices are generated on the GPU and resident in HBM before the timed region;
-the timed region covers exactly --steps updates after --warmup updates.
+the timed region covers exactly the last --steps updates of the stream (the
+steady state, at the largest ranks); the --warmup updates before it, and all
+earlier ones, run untimed.
 
 Prints one JSON line with the throughput, a roofline entry for the kernel group
 that takes the most device time (from HIP events recorded by the library on its
@@ -28,16 +30,18 @@ if ROOT not in sys.path:
 METRIC = "slices/s at eps-bounded error: bf16x3 MFMA vs FP32 path; TTM/Gram % roofline"
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0 / 3.0, "fp64": 78.6}
+# MFMA type of the residual Gram's products per path precision
+GRAM_PREC = {"fp32": "fp32", "bf16x3": "bf16x3", "fp64": "fp64"}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "blobs128_oracle_trajectory.json")
 
 WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_init=20,
                 tau=1e-4, seed=1001)
 
-# HBM bytes per launch of the dominant kernel of the FP32 headline run, from the
-# two counter passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, calibrated on a
-# 1 GiB copy) recorded in profiles/stream_update_blobs128x16_fp32_hbm_traffic.md.
-# Only reported while the kernel and workload are those the counters were taken on.
-MEASURED_TRAFFIC = {("fp32", "literal", "rot_v"): 1.436e9}
+# HBM bytes per launch of the dominant kernel of a run, from the two counter
+# passes (FETCH_SIZE, WRITE_SIZE; calibrated on a 1 GiB copy) recorded under
+# profiles/. Keyed by (precision, core update, kernel group); only reported
+# while the kernel and the timed window are those the counters were taken on.
+MEASURED_TRAFFIC = {}
 
 # Differentiation workload: a 96^3 x 8 variables x 16-slice window, ranks
 # (24, 24, 24, 6, 8).
@@ -88,6 +92,22 @@ def ttm_roofline(prof, precision):
                 achieved_tflops=round(p["flops"] / sec / 1e12, 3),
                 achieved_gbs=round(p["bytes"] / sec / 1e9, 1),
                 avg_ms=round(p["ms"] / p["launches"], 5), frac=round(t_floor / sec, 4))
+
+
+def gram_roofline(prof, precision):
+    """Roofline of the residual Gram over every growth of the whole stream
+    (growth is rare, so the timed window may hold none)."""
+    p = prof["gram"]
+    if not p["launches"] or p["ms"] <= 0:
+        return None
+    sec = p["ms"] / 1e3
+    peak_f = PEAK_TFLOPS[GRAM_PREC.get(precision, precision)]
+    t_floor = max(p["flops"] / (peak_f * 1e12), p["bytes"] / (PEAK_HBM_GBS * 1e9))
+    return dict(kernel="gram", launches=p["launches"], scope="whole stream",
+                achieved_tflops=round(p["flops"] / sec / 1e12, 3),
+                achieved_gbs=round(p["bytes"] / sec / 1e9, 1),
+                avg_ms=round(p["ms"] / p["launches"], 5), peak_tflops=peak_f,
+                frac=round(t_floor / sec, 4))
 
 
 def ttm_chain_flops(shape, modes_to):
@@ -233,36 +253,149 @@ def grad_bench(reps=5):
                 **out)
 
 
-def cpu_baseline(host_slices, n_init, tau, n_updates):
-    """The FP64 oracle on the host: init on the first slices (untimed), then
-    `n_updates` timed updates of the same stream."""
-    import numpy as np
-
-    from oracle import StreamingTucker as Oracle
-
+def cpu_info():
+    """CPU model and thread counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
         threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    x0 = np.stack(host_slices[:n_init], axis=-1)
-    orc = Oracle(x0, tau)
-    del x0
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count() or 1
+    return dict(model=model, blas_threads=int(threads), cpus_available=int(avail),
+                os_cpu_count=os.cpu_count())
+
+
+def cpu_baseline(host_slice, n_init, tau, n_updates, dims):
+    """The FP64 oracle on the host: init on the first slices (untimed), then
+    `n_updates` timed updates of the same stream. `host_slice(t)` returns slice
+    t in float64 (the float32 values the GPU consumes)."""
+    import numpy as np
+
+    from oracle import StreamingTucker as Oracle
+
+    info = cpu_info()
     t0 = time.perf_counter()
-    for t in range(n_init, n_init + n_updates):
-        orc.update(host_slices[t])
+    x0 = np.stack([host_slice(t).reshape(dims, order="F") for t in range(n_init)], axis=-1)
+    orc = Oracle(x0, tau)
+    init_s = time.perf_counter() - t0
+    del x0
+    slices = [host_slice(t).reshape(dims, order="F") for t in range(n_init, n_init + n_updates)]
+    t0 = time.perf_counter()
+    for y in slices:
+        orc.update(y)
     dt = time.perf_counter() - t0
-    return dict(value=round(n_updates / dt, 4), unit="slices/s", cores=int(threads),
+    return dict(value=round(n_updates / dt, 4), unit="slices/s", cores=info["blas_threads"],
                 kind="oracle",
                 sample=f"FP64 oracle updates of slices {n_init}..{n_init + n_updates - 1} of the "
-                       f"same stream after its untimed init on slices 0..{n_init - 1}; "
-                       f"{dt:.1f} s wall")
+                       f"same stream after its own init on slices 0..{n_init - 1} "
+                       f"({init_s:.1f} s, untimed); {dt:.1f} s timed; ranks after the sample "
+                       f"{list(orc.ranks)} (the GPU figure is taken at the end of the stream, "
+                       "where ranks are larger)",
+                cpu_model=info["model"], cpus_available=info["cpus_available"])
+
+
+def cpu_baseline_cfg0():
+    """The oracle on the 32 x 32 x 100 exactly-low-rank stream (tau 1e-3, init
+    10 slices), on one BLAS thread and on all of them."""
+    import numpy as np
+
+    from oracle import StreamingTucker as Oracle
+    from synth import CONFIGS, make_stream
+
+    c = CONFIGS[0]
+    s = make_stream(0)
+    sl = [s.slice_flat(t).astype(np.float32).astype(np.float64).reshape(s.dims, order="F")
+          for t in range(s.n_slices)]
+
+    def once():
+        orc = Oracle(np.stack(sl[:c["n_init"]], axis=-1), c["eps"])
+        t0 = time.perf_counter()
+        for t in range(c["n_init"], s.n_slices):
+            orc.update(sl[t])
+        return (s.n_slices - c["n_init"]) / (time.perf_counter() - t0), orc.ranks
+
+    out = dict(workload="32x32x100 exact rank (4,4,6) + noise, tau 1e-3, init 10 slices, "
+                        "90 updates")
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            v1, ranks = once()
+        out["one_thread"] = dict(value=round(v1, 2), unit="slices/s", cores=1)
+    except Exception as exc:  # pragma: no cover
+        out["one_thread"] = dict(error=repr(exc))
+    vall, ranks = once()
+    out["all_threads"] = dict(value=round(vall, 2), unit="slices/s",
+                              cores=cpu_info()["blas_threads"])
+    out["ranks"] = list(ranks)
+    return out
+
+
+def plan_window(n_slices, n_init, steps, warmup):
+    """Slice ranges of a benchmark run over the whole stream.
+
+    The initial ST-HOSVD takes slices [0, n_init); every later slice is one
+    update. The timed window is the LAST `steps` updates (the steady state, at
+    the largest ranks); the `warmup` updates just before it are the warm-up,
+    and all earlier updates run untimed (the state must go through them).
+    """
+    updates = n_slices - n_init
+    if steps < 1:
+        raise ValueError("--steps must be at least 1")
+    if warmup < 0:
+        raise ValueError("--warmup must be non-negative")
+    if steps + warmup > updates:
+        raise ValueError(f"--steps + --warmup = {steps + warmup} exceeds the {updates} updates "
+                         f"of the {n_slices}-slice stream (init {n_init})")
+    t0 = n_slices - steps
+    return dict(init=(0, n_init), untimed=(n_init, t0), warmup=(t0 - warmup, t0),
+                timed=(t0, n_slices))
+
+
+def probe_errors(st, golden_ck, pos_t):
+    """Element-wise comparison of GPU reconstructions with the oracle's at the
+    sampled positions of one golden checkpoint: max over its probe slices of
+    ||x^_gpu - x^_oracle|| / ||Y_t|| on the sample."""
+    import numpy as np
+
+    worst = 0.0
+    per = {}
+    for pr in golden_ck["probes"]:
+        rec = st.reconstruct_slice(pr["t"])
+        g = rec[pos_t].double().cpu().numpy()
+        o = np.asarray(pr["recon"])
+        x = np.asarray(pr["data"])
+        err = float(np.linalg.norm(g - o) / np.linalg.norm(x))
+        per[pr["t"]] = err
+        worst = max(worst, err)
+    return worst, per
+
+
+def guarded(name, fn, result):
+    """Run an optional benchmark leg; a failure is recorded, not fatal."""
+    try:
+        result[name] = fn()
+    except Exception as exc:  # the headline must survive an optional leg
+        log(f"{name} failed: {exc!r}")
+        result[name] = dict(error=repr(exc))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=375)
+    ap.add_argument("--steps", type=int, default=190,
+                    help="timed updates: the last STEPS updates of the 400-slice stream")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32")
     ap.add_argument("--core-update", choices=["literal", "factored"], default="literal",
@@ -278,6 +411,8 @@ def main():
                     help="skip the FP32 vs bf16x3 comparison on the 512x512x256 stream")
     ap.add_argument("--no-sine", action="store_true",
                     help="skip the sine-wave stream and batch run (100x100x5000)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline run (for profiling it alone)")
     ap.add_argument("--sine-only", action="store_true",
                     help="run only the sine-wave stream and batch run and print their "
                          "JSON (for profiling that workload alone)")
@@ -293,6 +428,15 @@ def main():
     if args.sine_only:
         print(json.dumps(dict(sine_wave=sine_bench())), flush=True)
         return
+    w = WORKLOAD
+    n_init, n_slices = w["n_init"], w["n_slices"]
+    try:
+        plan = plan_window(n_slices, n_init, args.steps, args.warmup)
+    except ValueError as exc:
+        raise SystemExit(str(exc))
+    if args.headline_only:
+        args.no_variants = args.no_cpu_baseline = args.no_large = True
+        args.no_sine = args.no_grad = True
 
     import numpy as np
     import torch
@@ -300,11 +444,6 @@ def main():
     import paper_2308_16395_amd as pkg
     from synth import BlobStream
 
-    w = WORKLOAD
-    n_init = w["n_init"]
-    total = n_init + args.warmup + args.steps
-    if total > w["n_slices"]:
-        raise SystemExit(f"warmup + steps exceed the {w['n_slices'] - n_init} updates of the stream")
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     if args.copy_probe:
@@ -315,19 +454,26 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 1 GiB read + 1 GiB written by one copy kernel")
         del src, dst
-    stream = BlobStream(w["space"], w["n_vars"], w["n_blobs"], n_slices=w["n_slices"],
+    stream = BlobStream(w["space"], w["n_vars"], w["n_blobs"], n_slices=n_slices,
                         seed=w["seed"])
     ny = math.prod(stream.dims)
-    log(f"generating {total} slices of {ny} elements on {torch.cuda.get_device_name(0)}")
-    data = torch.empty((total, ny), dtype=torch.float32, device=dev)
-    for t in range(total):
+    log(f"generating {n_slices} slices of {ny} elements on {torch.cuda.get_device_name(0)}")
+    data = torch.empty((n_slices, ny), dtype=torch.float32, device=dev)
+    for t in range(n_slices):
         data[t] = stream.slice_torch(t, dev, torch.float32)
     torch.cuda.synchronize()
+    log(f"plan: {plan}")
 
     golden = None
     if os.path.exists(GOLDEN):
         with open(GOLDEN) as f:
             golden = json.load(f)
+    pos_t = None
+    checkpoints = {}
+    if golden is not None and golden.get("probe_positions"):
+        pos_t = torch.tensor(golden["probe_positions"], dtype=torch.long, device=dev)
+        checkpoints = {ck["after"]: ck for ck in golden["checkpoints"]}
+    t_begin, t_end = plan["timed"]
 
     def run(precision, core_update):
         st = pkg.StreamingTucker(stream.dims, w["tau"], precision=precision, profile=True,
@@ -335,32 +481,43 @@ def main():
         t0 = time.perf_counter()
         st.init(data[:n_init].reshape(-1), n_init)
         init_s = time.perf_counter() - t0
-        traj = []
-        for t in range(n_init, n_init + args.warmup):
+        traj, guard, probe = [], 0, {}
+        for t in range(n_init, t_begin):
             st.update(data[t])
             traj.append(st.ranks)
-        st.profile(reset=True)
+            guard += st.stats()["guard_hits"]
+            if t in checkpoints and pos_t is not None:
+                probe[t] = probe_errors(st, checkpoints[t], pos_t)[0]
+        prof_untimed = st.profile(reset=True)
         ranks = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for t in range(n_init + args.warmup, total):
+        for t in range(t_begin, t_end):
             st.update(data[t])
             ranks.append(st.ranks)  # host-side counters only, no device sync
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         traj += ranks
         prof = st.profile()
+        whole = {g: {k: prof_untimed[g][k] + prof[g][k] for k in prof[g]} for g in prof}
         info = dict(value=round(args.steps / dt, 3), ms_per_step=round(1e3 * dt / args.steps, 4),
                     init_s=round(init_s, 3), ranks_final=list(st.ranks),
-                    recon_error_bound=st.recon_error()[0])
+                    recon_error_bound=st.recon_error()[0], guard_hits_untimed=guard)
         if golden is not None:
             ref = [tuple(x["ranks"]) for x in golden["slices"]][:len(traj)]
-            first = next((i for i, (a, b) in enumerate(zip(traj, ref)) if tuple(a) != b), None)
-            info["ranks_match_oracle"] = first is None
-            info["first_rank_divergence_slice"] = None if first is None else n_init + first
+            bad = [n_init + i for i, (a, b) in enumerate(zip(traj, ref)) if tuple(a) != b]
+            info["ranks_match_oracle"] = not bad
+            info["rank_divergent_slices"] = len(bad)
+            info["first_rank_divergence_slice"] = bad[0] if bad else None
+            if checkpoints.get(t_end - 1) is not None and pos_t is not None:
+                probe[t_end - 1], per = probe_errors(st, checkpoints[t_end - 1], pos_t)
+                info["oracle_error_final_probes"] = {str(k): v for k, v in per.items()}
+            if probe:
+                info["oracle_error_max_over_checkpoints"] = max(probe.values())
+                info["oracle_error_checkpoints"] = {str(k): v for k, v in probe.items()}
         if not args.no_accuracy:
             err2 = nrm2 = 0.0
-            for t in range(total):
+            for t in range(n_slices):
                 rec = st.reconstruct_slice(t)
                 err2 += torch.sum((rec.double() - data[t].double()) ** 2).item()
                 nrm2 += torch.sum(data[t].double() ** 2).item()
@@ -368,9 +525,9 @@ def main():
             info["eps_met"] = info["true_rel_error"] <= w["tau"]
         st.close()
         log(f"{precision} {core_update}: {info}")
-        return info, prof
+        return info, prof, whole
 
-    head, prof = run(args.precision, args.core_update)
+    head, prof, whole = run(args.precision, args.core_update)
     group, roof = roofline(prof, args.precision, args.core_update)
     result = {
         "metric": METRIC,
@@ -387,50 +544,60 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "advecting-blobs 128x128x128 x 16 variables, 400 slices, tau 1e-4, "
-                        "init 20 slices",
-            "slice_dims": list(stream.dims), "n_slices": w["n_slices"], "n_init": n_init,
+                        f"init 20 slices; timed: updates of slices {t_begin}..{t_end - 1} "
+                        "(the last steps of the stream), all slices resident in HBM",
+            "slice_dims": list(stream.dims), "n_slices": n_slices, "n_init": n_init,
             "eps": w["tau"], "precision": args.precision, "core_update": args.core_update,
-            "seed": w["seed"],
+            "seed": w["seed"], "timed_slices": [t_begin, t_end - 1],
         },
         "roofline": roof,
         "ttm_roofline": ttm_roofline(prof, args.precision),
+        "gram_roofline": gram_roofline(whole, args.precision),
         "kernels": {g: dict(launches=p["launches"], ms=round(p["ms"], 3),
                             tflops=round(p["flops"] / p["ms"] / 1e9, 3) if p["ms"] else None,
                             gbs=round(p["bytes"] / p["ms"] / 1e6, 1) if p["ms"] else None)
                     for g, p in prof.items() if p["launches"]},
     }
     result.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
+    if not args.no_cpu_baseline:
+        k = max(1, min(args.cpu_updates, n_slices - n_init))
+
+        def host_slice(t):
+            return data[t].cpu().numpy().astype(np.float64)
+
+        log(f"timing the FP64 oracle on {k} updates")
+        guarded("cpu_baseline",
+                lambda: cpu_baseline(host_slice, n_init, w["tau"], k, stream.dims), result)
+        guarded("cpu_baseline_cfg0", cpu_baseline_cfg0, result)
     if not args.no_variants:
         result["variants"] = {}
         for core in ("literal", "factored"):
             for prec in ("fp64", "bf16x3", "fp32"):
                 if (prec, core) == (args.precision, args.core_update):
                     continue
-                info, vprof = run(prec, core)
-                vg, vroof = roofline(vprof, prec, core)
-                info["roofline"] = vroof
-                info["ttm_ms"] = round(vprof["ttm1"]["ms"] + vprof["ttm"]["ms"], 3)
-                info["kernels_ms"] = {g: round(p["ms"], 2) for g, p in vprof.items()
-                                      if p["launches"]}
-                result["variants"][f"{prec}_{core}"] = info
-    if not args.no_cpu_baseline:
-        k = args.cpu_updates
-        host = [data[t].cpu().numpy().astype(np.float64).reshape(stream.dims, order="F")
-                for t in range(n_init + k)]
-        log(f"timing the FP64 oracle on {k} updates")
-        result["cpu_baseline"] = cpu_baseline(host, n_init, w["tau"], k)
-        del host
+
+                def variant(prec=prec, core=core):
+                    info, vprof, vwhole = run(prec, core)
+                    info["roofline"] = roofline(vprof, prec, core)[1]
+                    info["ttm_roofline"] = ttm_roofline(vprof, prec)
+                    info["gram_roofline"] = gram_roofline(vwhole, prec)
+                    info["ttm_ms"] = round(vprof["ttm1"]["ms"] + vprof["ttm"]["ms"], 3)
+                    info["kernels_ms"] = {g: round(p["ms"], 2) for g, p in vprof.items()
+                                          if p["launches"]}
+                    return info
+
+                guarded(f"{prec}_{core}", variant, result["variants"])
     del data
     torch.cuda.empty_cache()
     if not args.no_large:
         log("FP32 vs bf16x3 on the 512x512x256 stream")
-        result["large_stream"] = large_bench()
+        guarded("large_stream", large_bench, result)
     if not args.no_sine:
         log("sine-wave stream and batch ST-HOSVD (100x100x5000)")
-        result["sine_wave"] = sine_bench()
+        guarded("sine_wave", sine_bench, result)
     if not args.no_grad:
         log("timing Reconstruct/Project forward and VJPs")
-        result["differentiation"] = grad_bench()
+        guarded("differentiation", grad_bench, result)
     print(json.dumps(result), flush=True)
 
 
