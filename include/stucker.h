@@ -74,9 +74,13 @@ typedef struct st_config {
   double tau;                  /* relative error tolerance (the paper's tau), > 0 */
   int32_t precision;           /* enum st_precision */
   double orth_tol;             /* eps_m of the ISVD orthogonality check; 0 = 1e-5 */
-  double guard_rel;            /* relative guard band around each threshold test of
-                                  Alg. 4 in which ||E_k|| is re-evaluated with FP64
-                                  products; 0 = default (1e-2 FP32, 1e-1 bf16x3) */
+  double guard_rel;            /* relative guard band g of the reduced-precision
+                                  forms (R9): a slice whose ||E_k|| (Alg. 4) lies
+                                  above (1 - g) eps, or whose ISVD residual q
+                                  (Alg. 3) lies above (1 - g) eps, has its
+                                  decisions and state changes redone from FP64
+                                  products; 0 = default (3e-2 FP32, 1.5e-1
+                                  bf16x3); unused by ST_FP64 */
   int64_t max_rank_d;          /* cap on the streaming rank r_d; 0 = no cap */
   void *stream;                /* hipStream_t (of this library's HIP runtime) to
                                   run on; NULL = that runtime's null stream */
@@ -108,7 +112,9 @@ enum st_kernel_group {
   ST_K_ROT_V = 7,     /* V~ = [V v] V'' (mode-d TTM) */
   ST_K_ROT_C = 8,     /* core update, a mode-d TTM of [C; d] */
   ST_K_UD = 9,        /* U~_d update */
-  ST_K_GROUPS = 10
+  ST_K_REFINE = 10,   /* FP64-product coordinates of a slice and the ISVD correction
+                         sweep (reduced-precision forms, guard band) */
+  ST_K_GROUPS = 11
 };
 
 /* Accumulated timing of one kernel group since the last reset: launches, total
@@ -130,12 +136,22 @@ typedef struct st_slice_stats {
   double q;                           /* ||e|| of Alg. 3 */
   int32_t isvd_ignored;               /* 1 if q <= eps (e ignored) */
   int32_t qr_fired;                   /* 1 if the orthogonality check fired */
-  int32_t guard_hits;                 /* threshold tests re-evaluated in FP32 */
+  int32_t guard_hits;                 /* threshold tests re-evaluated with FP64
+                                         products (sum of the three refinements) */
   double orth_check;                  /* max_j |V(:,j)^T v| before any QR fix */
   double delta2;                      /* squared error this slice adds to the bound */
   double ms_total;                    /* wall time of the call, ms */
   double ms_modes;                    /* non-streaming modes (Alg. 4), ms */
   double ms_isvd;                     /* streaming mode (Alg. 3 + core update), ms */
+  int32_t refined_modes;              /* 1: a slice mode grew or fell in the guard band,
+                                         so every slice mode of this slice was redone
+                                         with FP64 products (reduced-precision forms) */
+  int32_t refined_isvd;               /* 1: q fell above (1 - g) eps with reduced-
+                                         precision coordinates, so d, p and q were
+                                         redone from FP64 products */
+  int32_t refined_gram;               /* residual Grams redone with FP64 products
+                                         because a tail sum of Alg. 1 fell in the
+                                         guard band of eps^2 */
 } st_slice_stats;
 
 typedef struct st_handle st_handle;

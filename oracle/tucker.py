@@ -169,6 +169,10 @@ def isvd(u, s, v, b, eps, eps_m=1e-12, cgs2=True):
     r = s.shape[0]
     p = v.T @ b
     e = b - v @ p
+    # diagnostic only: Alg. 3's orthogonality measure taken on the single-pass
+    # complement, max_j |V(:,j)^T e| / ||e|| (no effect on the result)
+    e1n = float(np.linalg.norm(e))
+    single = float(np.max(np.abs(v.T @ e)) / e1n) if r > 0 and e1n > 0 else 0.0
     if cgs2:
         p2 = v.T @ e
         e = e - v @ p2
@@ -195,7 +199,7 @@ def isvd(u, s, v, b, eps, eps_m=1e-12, cgs2=True):
     v2 = v2t.T
     u_new = np.vstack([u @ u2[:r, :], u2[r:r + 1, :]])
     v_new = v_prime @ v2
-    info = dict(p=p, q=q, ignored=q <= eps, qr=fired, u2=u2, v2=v2)
+    info = dict(p=p, q=q, ignored=q <= eps, qr=fired, u2=u2, v2=v2, orth_single_pass=single)
     return u_new, s_new, v_new, info
 
 
@@ -357,6 +361,6 @@ class StreamingTucker:
         self.xnorm2 += ynorm * ynorm
         self.disc += delta2
         rec.update(q=info["q"], ignored=bool(info["ignored"]), qr=info["qr"],
-                   delta2=delta2, ranks=self.ranks)
+                   orth_single_pass=info["orth_single_pass"], delta2=delta2, ranks=self.ranks)
         self.history.append(rec)
         return rec

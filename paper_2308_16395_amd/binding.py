@@ -50,7 +50,7 @@ EXPORTED = ["st_create", "st_init", "st_update", "st_ranks", "st_core", "st_fact
 ST_RECONSTRUCT, ST_PROJECT = 0, 1
 
 KERNEL_GROUPS = ["ttm1", "ttm", "gram", "eig", "ttm_ext", "isvd", "svd", "rot_v", "rot_c",
-                 "ud"]
+                 "ud", "refine"]
 
 
 class st_config(C.Structure):
@@ -92,6 +92,9 @@ class st_slice_stats(C.Structure):
         ("ms_total", C.c_double),
         ("ms_modes", C.c_double),
         ("ms_isvd", C.c_double),
+        ("refined_modes", C.c_int32),
+        ("refined_isvd", C.c_int32),
+        ("refined_gram", C.c_int32),
     ]
 
 
@@ -379,7 +382,9 @@ class StreamingTucker:
                     grew=[s.grew[k] for k in range(m)], q=s.q,
                     isvd_ignored=bool(s.isvd_ignored), qr_fired=bool(s.qr_fired),
                     guard_hits=s.guard_hits, orth_check=s.orth_check, delta2=s.delta2,
-                    ms_total=s.ms_total, ms_modes=s.ms_modes, ms_isvd=s.ms_isvd)
+                    ms_total=s.ms_total, ms_modes=s.ms_modes, ms_isvd=s.ms_isvd,
+                    refined_modes=bool(s.refined_modes), refined_isvd=bool(s.refined_isvd),
+                    refined_gram=s.refined_gram)
 
     def profile(self, reset=False):
         """Per kernel group: launches, device ms, algorithmic flops and bytes."""

@@ -147,6 +147,7 @@ struct st_handle {
   DBuf<double> U2, V2;
   DBuf<double> Wv;
   DBuf<float> Wc;
+  DBuf<double> dlt, pref;  // ISVD refinement: delta = d_exact - d, V^T delta and p
   // secular scratch
   DBuf<double> sd, sz, szh, smu, srot_cs, szz;
   DBuf<int> sact, sK, sdefl, sorg, srot_t, scounts;
@@ -157,7 +158,7 @@ struct st_handle {
   double *hS = nullptr, *hS_dev = nullptr;
   size_t hS_cap = 0;
   int64_t s_pending = 0;
-  size_t hpin_cap = 0;
+  size_t hpin_cap = 0, hpin_cap_prev = 0;
 
   // optional per-group timing with HIP events on `stream`
   bool profile = false;
@@ -272,17 +273,28 @@ struct st_handle {
     return ST_OK;
   }
 
+  // Pinned scratch for the scalars and short vectors the host reads back. It is
+  // separate from hS (a pending publication of the last update's singular
+  // values stays valid across a regrowth) and grows geometrically.
   hipError_t ensure_pinned(size_t count) {
     if (count <= hpin_cap) return hipSuccess;
-    (void)hipStreamSynchronize(stream);  // pending work may still write hS
-  if (hpin) (void)hipHostFree(hpin);
-  if (hS) (void)hipHostFree(hS);
-    hpin = nullptr;
+    // work queued by earlier calls may still read or write the old buffer
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = hpin_dev = nullptr;
     hpin_cap = 0;
-    hipError_t e = hipHostMalloc((void **)&hpin, count * sizeof(double), hipHostMallocDefault);
+    const size_t want = std::max(count, 2 * hpin_cap_prev);
+    e = hipHostMalloc((void **)&hpin, want * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&hpin_dev, hpin, 0);
-    if (e == hipSuccess) hpin_cap = count;
-    return e;
+    if (e != hipSuccess) {
+      if (hpin) (void)hipHostFree(hpin);
+      hpin = hpin_dev = nullptr;
+      return e;
+    }
+    hpin_cap = want;
+    hpin_cap_prev = want;
+    return hipSuccess;
   }
 
   // Norms of E and X for mode k into hpin[0..1].
@@ -391,11 +403,30 @@ struct st_handle {
     return e;
   }
 
+  // Tail band of the rank rule of Alg. 1 for a reduced-precision Gram, as a
+  // fraction of the Gram's trace: a tail sum within this band of eps^2 is
+  // decided again on the FP64 Gram.
+  double tail_band(GramPrec gp) const {
+    return gp == GramPrec::FP64 ? 0.0 : (gp == GramPrec::BF16X3 ? 1e-3 : 1e-5);
+  }
+  static bool tail_in_band(const std::vector<double> &desc, double eps, double band) {
+    if (band <= 0.0) return false;
+    double trace = 0.0;
+    for (double v : desc) trace += v;
+    const double e2 = eps * eps, w = band * std::max(trace, e2);
+    double tail = 0.0;
+    for (int64_t l = (int64_t)desc.size(); l >= 0; --l) {
+      if (std::fabs(tail - e2) <= w) return true;
+      if (l > 0) tail += desc[l - 1];
+    }
+    return false;
+  }
+  int exact_coords(const float *y, const double **dout);
   int do_init(const float *x0, int64_t n_init);
   int do_update(const float *y);
   int stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
                       double eps, st_slice_stats &stt, int &grow, double &q2, int64_t &c,
-                      int &v0next);
+                      int &v0next, bool exact_d, const float *y);
   hipError_t factored_product(const double *S_or_null, double *out64);
   int do_reconstruct_slice(int64_t t, float *out);
   void destroy();
@@ -559,6 +590,35 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
 }
 
 // ---------------------------------------------------------------------------
+// d = vec(Y x_1 U_1^T ... x_{d-1} U_{d-1}^T) at the current ranks with FP64
+// products (the exact coordinates of a slice whose slice modes all kept their
+// factors), into one of the two partial-core buffers.
+// ---------------------------------------------------------------------------
+int st_handle::exact_coords(const float *y, const double **dout) {
+  const void *x = y;
+  int x64 = 0, sel = 0;
+  for (int k = 0; k < m; ++k) {
+    const int64_t a = rprod(r, k), b = nprod(k + 1);
+    FiberIn in{};
+    in.x = x;
+    in.x64 = x64;
+    in.a = a;
+    in.n = n[k];
+    in.F = a * b;
+    tic();
+    hipError_t e = launch_fiber_project(in, wmat(k), 0, (int)r[k], FiberOut{D[sel].p, 1, a, r[k]},
+                                        nullptr, Prec::FP64, stream);
+    toc(ST_K_REFINE, 2.0 * in.F * n[k] * r[k], (x64 ? 8.0 : 4.0) * in.F * n[k] + 8.0 * in.F * r[k]);
+    if (e != hipSuccess) return hipfail(e, "FP64 slice coordinates");
+    x = D[sel].p;
+    x64 = 1;
+    sel ^= 1;
+  }
+  *dout = static_cast<const double *>(x);
+  return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Alg. 5.
 // ---------------------------------------------------------------------------
 int st_handle::do_update(const float *y) {
@@ -578,6 +638,10 @@ int st_handle::do_update(const float *y) {
   int dsel = 0;
   double delta2 = 0.0, eps = 0.0, ynorm2 = 0.0;
   int rc;
+  // reduced-precision products (FP32, bf16x3) decide only clear of the guard band
+  const bool fast = prec != Prec::FP64;
+  Prec mp = prec;             // product precision of the per-mode loop below
+  bool exact_d = !fast;       // d = vec(D*_{d-1}) carries FP64 products
   // Every mode is first projected at the current ranks, the case of no growth
   // (Alg. 4 keeping U_k for every k), and the residual norms of all modes come
   // back with one synchronisation. From the first mode whose test fails or
@@ -627,11 +691,24 @@ int st_handle::do_update(const float *y) {
       const double e2 = hpin[2 * k0];
       if (!std::isfinite(e2)) return fail(ST_ENONFINITE, "non-finite residual in mode %d", k0 + 1);
       const double en = std::sqrt(e2);
-      if (en > eps || (prec != Prec::FP64 && std::fabs(en - eps) <= guard_rel * eps)) break;
+      // keep U_k only when the test passes clear of the guard band (R9); the
+      // FP64 form decides on its own products
+      if (fast ? en > (1.0 - guard_rel) * eps : en > eps) break;
       stt.e_norm[k0] = en;
       delta2 += e2;
     }
-    if (k0 > 0) {
+    if (fast && k0 < m) {
+      // A slice mode grows or lies near its threshold: the decisions of this
+      // slice and the new factor columns must not depend on reduced-precision
+      // products, so every slice mode is redone from Y with FP64 products.
+      k0 = 0;
+      delta2 = 0.0;
+      for (int k = 0; k < m; ++k) stt.e_norm[k] = 0.0;
+      mp = Prec::FP64;
+      exact_d = true;
+      stt.refined_modes = 1;
+      ++stt.guard_hits;
+    } else if (k0 > 0) {
       Din = Dspec[k0 - 1].p;
       din64 = 1;
     }
@@ -648,7 +725,9 @@ int st_handle::do_update(const float *y) {
     in.F = a * b;
     double *Dout = D[dsel].p;
     const int tgroup = k == 0 ? ST_K_TTM1 : ST_K_TTM;
-    rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, 1, a, r[k]}, prec, tgroup);
+    // (this loop only runs with FP64 products: the FP64 form, or a refined slice)
+    rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, 1, a, r[k]}, mp,
+                       fast ? ST_K_REFINE : tgroup);
     if (rc != ST_OK) return rc;
     double e2 = hpin[0];
     if (k == 0) {
@@ -657,13 +736,6 @@ int st_handle::do_update(const float *y) {
       eps = tau * std::sqrt(ynorm2 / d);
     }
     if (!std::isfinite(e2)) return fail(ST_ENONFINITE, "non-finite residual in mode %d", k + 1);
-    if (prec != Prec::FP64 && std::fabs(std::sqrt(e2) - eps) <= guard_rel * eps) {
-      // close to the threshold: decide with the FP64 products
-      rc = project_resid(in, wmat(k), (int)r[k], FiberOut{Dout, 1, a, r[k]}, Prec::FP64, tgroup);
-      if (rc != ST_OK) return rc;
-      e2 = hpin[0];
-      ++stt.guard_hits;
-    }
     stt.e_norm[k] = std::sqrt(e2);
     if (std::sqrt(e2) <= eps) {  // Alg. 4: keep U_k, D*_k = P_k
       delta2 += e2;
@@ -672,15 +744,24 @@ int st_handle::do_update(const float *y) {
       dsel ^= 1;
       continue;
     }
-    // Alg. 4 growth: TruncatedSVD of E_(k) via its Gram (Alg. 1)
-    rc = gram_eig(in, wmat(k), (int)r[k], nk,
-                  prec == Prec::FP64 ? GramPrec::FP64
-                                     : (prec == Prec::BF16X3 ? GramPrec::BF16X3 : GramPrec::FP32),
-                  prec == Prec::FP64);
+    // Alg. 4 growth: TruncatedSVD of E_(k) via its Gram (Alg. 1). E is
+    // recomputed with FP64 products; the Gram's own products take the form's
+    // precision, and a tail sum within the band of eps^2 is decided again on
+    // the FP64 Gram.
+    const GramPrec gp = prec == Prec::FP64 ? GramPrec::FP64
+                        : (prec == Prec::BF16X3 ? GramPrec::BF16X3 : GramPrec::FP32);
+    rc = gram_eig(in, wmat(k), (int)r[k], nk, gp, true);
     if (rc != ST_OK) return rc;
     int64_t rp;
     double tail;
     rank_rule(hpin, nk, eps, rp, tail, desc);
+    if (tail_in_band(desc, eps, tail_band(gp))) {
+      rc = gram_eig(in, wmat(k), (int)r[k], nk, GramPrec::FP64, true);
+      if (rc != ST_OK) return rc;
+      rank_rule(hpin, nk, eps, rp, tail, desc);
+      ++stt.refined_gram;
+      ++stt.guard_hits;
+    }
     rp = std::min<int64_t>(rp, nk - r[k]);
     if (rp <= 0) {  // the Gram resolves nothing above the tolerance
       delta2 += e2;
@@ -699,7 +780,7 @@ int st_handle::do_update(const float *y) {
     // D*_k = D*_{k-1} x_k [U_k W_k]^T
     tic();
     e = launch_fiber_project(in, wmat(k), 0, (int)rn[k], FiberOut{Dout, 1, a, rn[k]}, nullptr,
-                             prec, stream);
+                             mp, stream);
     toc(ST_K_TTM_EXT, 2.0 * in.F * nk * rn[k],
         (din64 ? 8.0 : 4.0) * in.F * nk + 8.0 * in.F * rn[k]);
     if (e != hipSuccess) return hipfail(e, "extended projection");
@@ -720,12 +801,13 @@ int st_handle::do_update(const float *y) {
     if (rn[k] != r[k]) map.identity = 0;
   }
   if (!din64) return fail(ST_EINVAL, "slice has no slice modes");
-  const double *dvec = static_cast<const double *>(Din);
+  const double *dvec = static_cast<const double *>(Din);  // (replaced by exact coordinates
+                                                          // when the ISVD is refined)
   if (factored) {
     int growf = 0, v0next = v0cur;
     double q2f = 0.0;
     int64_t cf = 0;
-    rc = stream_factored(map, dvec, Rold, Rnew, eps, stt, growf, q2f, cf, v0next);
+    rc = stream_factored(map, dvec, Rold, Rnew, eps, stt, growf, q2f, cf, v0next, exact_d, y);
     if (rc != ST_OK) return rc;
     // ---- commit (the singular values follow through hS) ----
     s_pending = cf;
@@ -784,16 +866,61 @@ int st_handle::do_update(const float *y) {
   settle();
   // q^2 = ||e1 - V p2||^2 = ||e1||^2 - ||p2||^2 (V orthonormal; p2 ~ u ||d||)
   const double e1sq = hpin[0];
-  double p2sq = 0.0;
-  for (int j = 0; j < rdi; ++j) p2sq += hpin[3 + rdi + j] * hpin[3 + rdi + j];
-  const double q2 = std::max(e1sq - p2sq, 0.0);
-  const double q = std::sqrt(q2);
-  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
-  double pmax = 0.0, p2max = 0.0;
+  double p2sq = 0.0, p2max = 0.0;
   for (int j = 0; j < rdi; ++j) {
-    pmax = std::max(pmax, std::fabs(hpin[3 + j]));
+    p2sq += hpin[3 + rdi + j] * hpin[3 + rdi + j];
     p2max = std::max(p2max, std::fabs(hpin[3 + rdi + j]));
   }
+  double q2 = std::max(e1sq - p2sq, 0.0);
+  double q = std::sqrt(q2);
+  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+  const double *pvec = p.p;  // p of Alg. 3 on the device
+  std::vector<double> ph(hpin + 3, hpin + 3 + rdi);
+  if (!exact_d && q > (1.0 - guard_rel) * eps) {
+    // The slice may grow V (or lies near the threshold): q, p and the new
+    // column must come from FP64 products. With d' = d + delta the exact
+    // coordinates, p' = p + V^T delta and, since e = d - V p is orthogonal to
+    // V, ||e'||^2 = q^2 + 2 (d.delta - p.V^T delta) + ||delta||^2
+    // - ||V^T delta||^2: one sweep over V instead of both passes again.
+    const double *dex = nullptr;
+    rc = exact_coords(y, &dex);
+    if (rc != ST_OK) return rc;
+    const int nbd = 1024;
+    e = dlt.ensure((size_t)Rnew);
+    if (e == hipSuccess) e = pref.ensure(2 * (size_t)rdi + 2);
+    if (e == hipSuccess) e = part.ensure(2 * (size_t)nbd);
+    if (e != hipSuccess) return hipfail(e, "isvd refinement buffers");
+    double *vtd = pref.p, *pnew = pref.p + rdi;
+    tic();
+    e = launch_delta(dex, dvec, Rnew, dlt.p, part.p, nbd, stream);
+    if (e == hipSuccess) e = launch_reduce_pairs(part.p, nbd, sums.p + 16, stream);
+    if (e == hipSuccess)
+      e = launch_gemv_t_mapped(V[cur].p, Rold, map, Rnew, rdi, dlt.p, colpart.p, nbg, stream);
+    if (e == hipSuccess && rdi > 0)
+      e = launch_colsum(colpart.p, nbg, rdi, vtd, p.p, pnew, nullptr, nullptr, stream);
+    toc(ST_K_REFINE, 2.0 * Rnew * rdi + 4.0 * Rnew, 8.0 * Rold * rdi + 24.0 * Rnew);
+    if (e == hipSuccess)
+      e = launch_gather3(hpin_dev, sums.p + 16, 2, 0, vtd, rdi, 2, pnew, rdi, 2 + rdi, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "isvd refinement");
+    settle();
+    double pv = 0.0, vv = 0.0;
+    for (int j = 0; j < rdi; ++j) {
+      pv += ph[j] * hpin[2 + j];
+      vv += hpin[2 + j] * hpin[2 + j];
+    }
+    q2 = std::max(q2 + 2.0 * (hpin[0] - pv) + hpin[1] - vv, 0.0);
+    q = std::sqrt(q2);
+    if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+    ph.assign(hpin + 2 + rdi, hpin + 2 + 2 * rdi);
+    dvec = dex;
+    pvec = pnew;
+    exact_d = true;
+    stt.refined_isvd = 1;
+    ++stt.guard_hits;
+  }
+  double pmax = 0.0;
+  for (int j = 0; j < rdi; ++j) pmax = std::max(pmax, std::fabs(ph[j]));
   const double tol = 8.0 * 0x1p-53 * std::max({S_host.empty() ? 0.0 : S_host[0], pmax, q});
   const int grow = (q > eps && q > tol) ? 1 : 0;
   const int64_t c = rd + grow;
@@ -827,7 +954,7 @@ int st_handle::do_update(const float *y) {
   ud_ld[nxt] = ldn;
 
   tic();
-  e = launch_secular_svd(secdata(rdi), S[cur].p, p.p, q, grow, tol, (int)c, U2.p, V2.p,
+  e = launch_secular_svd(secdata(rdi), S[cur].p, pvec, q, grow, tol, (int)c, U2.p, V2.p,
                          S[nxt].p, stream);
   if (e == hipSuccess)
     e = launch_build_rot_w(U2.p, V2.p, rdi, (int)c, (int)kv, grow ? 1.0 / q : 0.0, Wv.p, ldwv,
@@ -847,7 +974,7 @@ int st_handle::do_update(const float *y) {
   tic();
   // V~ = [V v] V'' with v = e / q, e = d - V p formed per row in FP64
   e = launch_rot64(vin, Wv.p, 1, ldwv, 0, (int)c, FiberOut{V[nxt].p, 1, Rnew, c}, grow ? 2 : 0,
-                   p.p, stream);
+                   pvec, stream);
   // read V (R_old x r_d, FP64) and d, write V~ (R_new x c, FP64): 2 R_new K c flops
   toc(ST_K_ROT_V, 2.0 * Rnew * (double)kv * c + (grow ? 2.0 * Rnew * rd : 0.0),
       8.0 * ((double)Rold * rd + (grow ? Rnew : 0) + (double)Rnew * c));
@@ -911,7 +1038,7 @@ int st_handle::do_update(const float *y) {
 // ---------------------------------------------------------------------------
 int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
                                double eps, st_slice_stats &stt, int &grow, double &q2,
-                               int64_t &c, int &v0next) {
+                               int64_t &c, int &v0next, bool exact_d, const float *y) {
   const int rdi = (int)rd;
   const int nxt = cur ^ 1;
   hipError_t e = hipSuccess;
@@ -948,60 +1075,78 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   double *w1 = wvec.p, *w2 = wvec.p + rdi, *ws = wvec.p + 2 * rdi, *gv = wvec.p + 3 * rdi;
   double *sc = sums.p + 8;  // [0] ||e1||^2, [1] q^2, [2] cancelled magnitude
   double *dd = sums.p + 12, *ee = sums.p + 13;
-  tic();
-  e = launch_gemv_t(V0, Rnew, rdi, dvec, colpart.p, nbg, stream);
-  if (e == hipSuccess)
-    e = launch_colsum(colpart.p, nbg, rdi, t1, nullptr, nullptr, colpart.p + (size_t)rdi * nbg,
-                      dd, stream);
-  if (e == hipSuccess)
-    e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, nullptr,
-                         stream);
-  // V0 and d read once (FP64); r x r products
-  toc(ST_K_ISVD, 2.0 * Rnew * rdi + 10.0 * (double)rdi * rdi, 8.0 * Rnew * (rdi + 1.0));
-  if (e == hipSuccess)
-    e = launch_gather3(hpin_dev, sc, 3, 0, p.p, rdi, 3, p2.p, rdi, 3 + rdi, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return hipfail(e, "isvd projections");
-  settle();
-  double e1sq = hpin[0];
-  q2 = std::max(hpin[1], 0.0);
-  double q = std::sqrt(q2);
-  // rounding bound of the cancelled sum forming q^2, as a bound on q
-  const double dq2 = 64.0 * 0x1p-53 * hpin[2];
-  const double dq = q > 0.0 ? dq2 / (2.0 * q) : std::sqrt(dq2);
-  if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
-  if (std::fabs(q - eps) <= 4.0 * dq) {
-    // too close to call from G0: redo the second pass exactly over V0
-    RowMap ident{};
-    ident.nm = m;
-    ident.identity = 1;
-    IsvdArgs ia{};
-    ia.V = V0;
-    ia.ldv = Rnew;
-    ia.r = rdi;
-    ia.R = Rnew;
-    ia.map = ident;
-    ia.d = dvec;
-    ia.p1 = w1;
-    ia.colpart = colpart.p;
-    ia.q2part = q2part.p;
+  double e1sq = 0.0, q = 0.0;
+  for (int attempt = 0;; ++attempt) {
+    const int igroup = attempt ? ST_K_REFINE : ST_K_ISVD;
     tic();
-    e = launch_isvd_pass(2, ia, nbp, stream);
+    e = launch_gemv_t(V0, Rnew, rdi, dvec, colpart.p, nbg, stream);
     if (e == hipSuccess)
-      e = launch_colsum(colpart.p, nbp, rdi, t2, nullptr, nullptr, q2part.p, sc, stream);
+      e = launch_colsum(colpart.p, nbg, rdi, t1, nullptr, nullptr, colpart.p + (size_t)rdi * nbg,
+                        dd, stream);
     if (e == hipSuccess)
-      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv,
-                           nullptr, stream);
-    toc(ST_K_ISVD, 4.0 * Rnew * rdi, 8.0 * Rnew * (rdi + 1.0));
+      e = launch_isvd_gram(M, G0, rdi, t1, dd, 0, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv, nullptr,
+                           stream);
+    // V0 and d read once (FP64); r x r products
+    toc(igroup, 2.0 * Rnew * rdi + 10.0 * (double)rdi * rdi, 8.0 * Rnew * (rdi + 1.0));
     if (e == hipSuccess)
       e = launch_gather3(hpin_dev, sc, 3, 0, p.p, rdi, 3, p2.p, rdi, 3 + rdi, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hipfail(e, "exact second pass");
+    if (e != hipSuccess) return hipfail(e, "isvd projections");
     settle();
     e1sq = hpin[0];
     q2 = std::max(hpin[1], 0.0);
     q = std::sqrt(q2);
-    ++stt.guard_hits;
+    // rounding bound of the cancelled sum forming q^2, as a bound on q
+    const double dq2 = 64.0 * 0x1p-53 * hpin[2];
+    const double dq = q > 0.0 ? dq2 / (2.0 * q) : std::sqrt(dq2);
+    if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+    if (std::fabs(q - eps) <= 4.0 * dq) {
+      // too close to call from G0: redo the second pass exactly over V0
+      RowMap ident{};
+      ident.nm = m;
+      ident.identity = 1;
+      IsvdArgs ia{};
+      ia.V = V0;
+      ia.ldv = Rnew;
+      ia.r = rdi;
+      ia.R = Rnew;
+      ia.map = ident;
+      ia.d = dvec;
+      ia.p1 = w1;
+      ia.colpart = colpart.p;
+      ia.q2part = q2part.p;
+      tic();
+      e = launch_isvd_pass(2, ia, nbp, stream);
+      if (e == hipSuccess)
+        e = launch_colsum(colpart.p, nbp, rdi, t2, nullptr, nullptr, q2part.p, sc, stream);
+      if (e == hipSuccess)
+        e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv,
+                             nullptr, stream);
+      toc(igroup, 4.0 * Rnew * rdi, 8.0 * Rnew * (rdi + 1.0));
+      if (e == hipSuccess)
+        e = launch_gather3(hpin_dev, sc, 3, 0, p.p, rdi, 3, p2.p, rdi, 3 + rdi, stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) return hipfail(e, "exact second pass");
+      settle();
+      e1sq = hpin[0];
+      q2 = std::max(hpin[1], 0.0);
+      q = std::sqrt(q2);
+      ++stt.guard_hits;
+    }
+    if (!exact_d && q > (1.0 - guard_rel) * eps) {
+      // The slice may grow V (or lies near the threshold): redo the projection
+      // from FP64-product coordinates, so the test and the appended column of V0
+      // carry no reduced-precision rounding.
+      const double *dex = nullptr;
+      const int rc2 = exact_coords(y, &dex);
+      if (rc2 != ST_OK) return rc2;
+      dvec = dex;
+      exact_d = true;
+      stt.refined_isvd = 1;
+      ++stt.guard_hits;
+      continue;
+    }
+    break;
   }
   double pmax = 0.0, p2max = 0.0;
   for (int j = 0; j < rdi; ++j) {
@@ -1222,6 +1367,9 @@ void st_handle::destroy() {
   srot_t.release();
   scounts.release();
   if (hpin) (void)hipHostFree(hpin);
+  if (hS) (void)hipHostFree(hS);
+  hpin = hpin_dev = hS = hS_dev = nullptr;
+  hpin_cap = hS_cap = 0;
   for (auto &pd : pending) {
     event_pool.push_back(pd.a);
     event_pool.push_back(pd.b);

@@ -887,6 +887,38 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const double *V0, int64_t l
   }
 }
 
+// delta = a - b over n rows, and per block the pair (sum b * delta, sum
+// delta^2) into part[2 * block]; reduced afterwards in a fixed order. Used to
+// move the ISVD quantities of a slice from coordinates b (reduced-precision
+// products) to the exact coordinates a without a second pass over V.
+__global__ __launch_bounds__(256) void delta_kernel(const double *a, const double *b, int64_t n,
+                                                    double *delta, double *part) {
+  __shared__ double red[16];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double bi = b[i];
+    const double dl = a[i] - bi;
+    delta[i] = dl;
+    s1 += bi * dl;
+    s2 += dl * dl;
+  }
+  s1 = block_sum(s1, red);
+  s2 = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+hipError_t launch_delta(const double *a, const double *b, int64_t n, double *delta, double *part,
+                        int nblocks, hipStream_t s) {
+  if (nblocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(delta_kernel, dim3((unsigned)nblocks), dim3(256), 0, s, a, b, n, delta,
+                     part);
+  return hipGetLastError();
+}
+
 int gemv_t_blocks(int64_t R) {
   const int64_t t = (R + kGemvRows - 1) / kGemvRows;
   return (int)(t > 0 ? t : 1);

@@ -93,6 +93,10 @@ hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const doub
 hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
                             double inv_q, int grow, double *Gn, hipStream_t s);
 hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s);
+// delta = a - b (n rows) and per-block pairs (sum b * delta, sum delta^2) in
+// part[2 * nblocks] (reduce with launch_reduce_pairs).
+hipError_t launch_delta(const double *a, const double *b, int64_t n, double *delta, double *part,
+                        int nblocks, hipStream_t s);
 
 // Message for st_last_error(NULL) after a failed stateless call.
 void set_stateless_error(const char *msg);

@@ -12,7 +12,11 @@ at a fixed seeded sample of element positions, together with the data values
 there, so a GPU run can be compared with the oracle element by element on
 reconstructed slices (sampled outputs; the full slices would be 268 MB each).
 
-Usage: python tests/golden/make_blob_trajectory.py [n_slices]
+With the argument ``factored`` the oracle keeps the core as C = V x_d S (its
+core_update="factored"); the decisions are the same, the reconstructions of
+the ignored residuals differ, and the output goes to a second file.
+
+Usage: python tests/golden/make_blob_trajectory.py [n_slices] [literal|factored]
 """
 
 import json
@@ -41,6 +45,7 @@ def sample_positions(ny, n=N_SAMPLES, seed=SAMPLE_SEED):
 
 def main():
     n_slices = int(sys.argv[1]) if len(sys.argv) > 1 else 400
+    core_update = sys.argv[2] if len(sys.argv) > 2 else "literal"
     s = make_stream(1)
     n_init, tau = 20, 1e-4
     ny = int(np.prod(s.dims))
@@ -52,9 +57,11 @@ def main():
     def sl(t):
         return flat32(t).reshape(s.dims, order="F")
 
-    orc = StreamingTucker(np.stack([sl(t) for t in range(n_init)], axis=-1), tau)
+    orc = StreamingTucker(np.stack([sl(t) for t in range(n_init)], axis=-1), tau,
+                          core_update=core_update)
     out = dict(
         source="FP64 oracle (oracle/tucker.py), blob stream config 1, float32 slice values",
+        core_update=core_update,
         stream=dict(space=list(s.space), n_vars=s.n_vars, n_blobs=s.n_blobs, seed=1001,
                     n_init=n_init, tau=tau, n_slices=n_slices),
         init_ranks=list(orc.ranks), init_bound=orc.recon_error_bound(), slices=[],
@@ -77,7 +84,9 @@ def main():
                                    slice_norm=float(np.linalg.norm(flat32(tp)))))
             out["checkpoints"].append(dict(after=t, probes=probes))
         print(t, orc.ranks, f"{time.time() - t0:.0f}s", flush=True)
-    with open(os.path.join(HERE, "blobs128_oracle_trajectory.json"), "w") as f:
+    name = ("blobs128_oracle_trajectory.json" if core_update == "literal"
+            else f"blobs128_oracle_trajectory_{core_update}.json")
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f)
 
 

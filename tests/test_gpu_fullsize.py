@@ -1,12 +1,18 @@
 """GPU at full size: the 128^3 x 16 blob stream (400 slices, tau = 1e-4) in the
-launch configuration the benchmark times.
+launch configuration the benchmark times, in every precision and core form.
 
 The oracle cannot keep up at this size inside a test, so its per-slice
-decisions were recorded once by tests/golden/make_blob_trajectory.py (oracle
-only). With exact FP64 products on the FP32 data the GPU must reproduce the
-rank after every slice. Properties that hold at any size are checked on the
-final state: the certified bound and the true error are within tau, the
-factors are orthonormal, V is row-orthonormal and S is positive and sorted.
+decisions, and its reconstructions of probe slices at checkpoints (at a seeded
+sample of element positions), were recorded once by
+tests/golden/make_blob_trajectory.py (oracle only). Every form must reproduce
+the oracle's ranks after every slice: the FP64 form decides on exact products,
+the FP32 and bf16x3 forms redo every decision that lies within their guard band
+and every growth from FP64 products. The reconstructions must match the
+oracle's element by element on the sample within 1e-5 (FP64, FP32) / 1e-4
+(bf16x3) of the slice norm at every checkpoint. Properties that hold at any
+size are checked on the final state: the certified bound and the true error are
+within tau, the factors are orthonormal, V is column-orthonormal and S is
+positive and sorted.
 """
 
 import json
@@ -19,6 +25,10 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "blobs128_oracle_trajectory.json")
+# the oracle run with the core kept as C = V x_d S: the same decisions, and the
+# reconstructions the factored form must match
+GOLDEN_FACTORED = os.path.join(os.path.dirname(__file__), "golden",
+                               "blobs128_oracle_trajectory_factored.json")
 
 
 def _stream():
@@ -33,6 +43,12 @@ def _run(precision, core_update="literal"):
 
     with open(GOLDEN) as f:
         golden = json.load(f)
+    probes = golden
+    if core_update == "factored":
+        probes = {}
+        if os.path.exists(GOLDEN_FACTORED):
+            with open(GOLDEN_FACTORED) as f:
+                probes = json.load(f)
     s = _stream()
     dev = torch.device("cuda:0")
     n_init, tau, n = 20, 1e-4, golden["stream"]["n_slices"]
@@ -40,11 +56,21 @@ def _run(precision, core_update="literal"):
     st = pkg.StreamingTucker(s.dims, tau, precision=precision, core_update=core_update)
     st.init(x0, n_init)
     assert list(st.ranks) == golden["init_ranks"]
-    traj = []
+    pos = torch.tensor(probes.get("probe_positions", []), dtype=torch.long, device=dev)
+    cks = {ck["after"]: ck for ck in probes.get("checkpoints", [])}
+    traj, probe_err, stats = [], {}, []
     for t in range(n_init, n):
         st.update(s.slice_torch(t, dev, torch.float32))
         traj.append(tuple(st.ranks))
-    return st, s, golden, traj
+        stats.append(st.stats())
+        if t in cks:
+            worst = 0.0
+            for pr in cks[t]["probes"]:
+                g = st.reconstruct_slice(pr["t"])[pos].double().cpu().numpy()
+                o = np.asarray(pr["recon"])
+                worst = max(worst, float(np.linalg.norm(g - o) / np.linalg.norm(pr["data"])))
+            probe_err[t] = worst
+    return st, s, golden, traj, probe_err, stats
 
 
 def _true_error(st, s, n):
@@ -59,41 +85,52 @@ def _true_error(st, s, n):
     return math.sqrt(err2 / nrm2)
 
 
+FORMS = [("fp64", "literal", 1e-5), ("fp64", "factored", 1e-5), ("fp32", "literal", 1e-5),
+         ("fp32", "factored", 1e-5), ("bf16x3", "literal", 1e-4), ("bf16x3", "factored", 1e-4)]
+
+
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle trajectory not generated")
-@pytest.mark.parametrize("core_update", ["literal", "factored"])
-def test_fp64_products_reproduce_every_oracle_decision(core_update):
-    """The rank decisions do not depend on how the core is carried, so both
-    forms must follow the same recorded trajectory."""
+@pytest.mark.parametrize("precision,core_update,err_tol", FORMS,
+                         ids=[f"{p}-{c}" for p, c, _ in FORMS])
+def test_every_form_reproduces_every_oracle_decision(precision, core_update, err_tol):
+    """The rank decisions do not depend on how the core is carried or on the
+    product precision (decisions near a threshold and every growth are taken
+    on FP64 products), so every form follows the recorded trajectory."""
     import torch
 
-    st, s, golden, traj = _run("fp64", core_update)
+    st, s, golden, traj, probe_err, stats = _run(precision, core_update)
     ref = [tuple(x["ranks"]) for x in golden["slices"]]
+    assert len(traj) == len(ref)
     for i, (a, b) in enumerate(zip(traj, ref)):
-        assert a == b, (20 + i, a, b, golden["slices"][i]["q_over_eps"])
+        g = golden["slices"][i]
+        assert a == b, (20 + i, a, b, g["q_over_eps"], g["e_over_eps"])
+    # element-wise agreement with the oracle's reconstructions at every checkpoint
+    assert probe_err, "the golden file holds no probe checkpoints"
+    assert max(probe_err.values()) <= err_tol, probe_err
     tau = golden["stream"]["tau"]
     bound, _ = st.recon_error()
     assert bound <= tau
-    np.testing.assert_allclose(bound, golden["slices"][-1]["bound"], rtol=1e-3)
+    # The bound sums the squared residual norms the path measured. Split-bf16
+    # products add their own rounding (about 0.15 eps in ||E_k|| at this tau) to
+    # every kept residual, so that bound sits a few percent above the oracle's;
+    # FP32 and FP64 products agree with it to 1e-3.
+    np.testing.assert_allclose(bound, golden["slices"][-1]["bound"],
+                               rtol=5e-2 if precision == "bf16x3" else 1e-3)
+    assert bound >= golden["slices"][-1]["bound"] * (1 - 1e-3)
     assert _true_error(st, s, golden["stream"]["n_slices"]) <= tau
     for k in range(st.d):
         u = st.factor(k)
-        g = u.T @ u
-        assert torch.max(torch.abs(g - torch.eye(g.shape[0], device=g.device, dtype=g.dtype))) < 1e-6
+        gm = u.T @ u
+        assert torch.max(torch.abs(gm - torch.eye(gm.shape[0], device=gm.device,
+                                                  dtype=gm.dtype))) < 1e-6
     v = st.aux_v().double()
-    g = v.T @ v
-    assert torch.max(torch.abs(g - torch.eye(g.shape[0], device=g.device, dtype=g.dtype))) < 1e-5
+    gm = v.T @ v
+    assert torch.max(torch.abs(gm - torch.eye(gm.shape[0], device=gm.device,
+                                              dtype=gm.dtype))) < 1e-5
     sv = st.sv()
     assert all(x > 0 for x in sv) and all(a >= b for a, b in zip(sv, sv[1:]))
-
-
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle trajectory not generated")
-@pytest.mark.parametrize("precision,core_update",
-                         [("fp32", "literal"), ("bf16x3", "literal"), ("fp32", "factored")])
-def test_fast_forms_meet_tau_at_full_size(precision, core_update):
-    st, s, golden, traj = _run(precision, core_update)
-    tau = golden["stream"]["tau"]
-    bound, _ = st.recon_error()
-    assert bound <= tau
-    assert _true_error(st, s, golden["stream"]["n_slices"]) <= tau
-    # the spatial ranks settle where the oracle's do
-    assert traj[-1][:4] == tuple(golden["slices"][-1]["ranks"][:4])
+    if precision != "fp64":
+        # the guard band is what keeps the decisions: report how often it fired
+        hits = sum(x["guard_hits"] for x in stats)
+        print(f"{precision} {core_update}: {hits} refinements over {len(stats)} slices, "
+              f"probe error {max(probe_err.values()):.2e}")
