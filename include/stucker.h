@@ -236,6 +236,22 @@ int st_reconstruct_slice(const st_handle *h, int64_t t, float *out);
 int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
            int64_t rows, float *out, double *norms, int32_t precision, void *stream);
 
+/* st_ttm for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc). Same
+ * arguments, results and errors as st_ttm; it calls no hipMalloc/hipFree and
+ * no allocating library routine. Its scratch (the per-block residual-norm
+ * partials, their sum, and the FP64 or split-bf16 copy of A for those
+ * precisions) lives in one fixed 8 MiB device array per GPU, held until the
+ * process ends; a call that would need more (about 2^25 fibres with norms, or
+ * rows x dims[mode] above about 10^6 elements in FP64) returns ST_EINVAL with
+ * the reason in st_last_error(NULL). Every call on a GPU shares that GPU's
+ * array and leaves its contents behind: calls that overlap on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller. The
+ * array's device address is looked up once per device on the first call. */
+int st_ttm_noalloc(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode,
+                   const float *a, int64_t rows, float *out, double *norms, int32_t precision,
+                   void *stream);
+
 /* Stateless mode-k Gram (Alg. 1, first line) of a dense column-major float32
  * device tensor: G = E_(mode) E_(mode)^T with E = X - (X x_mode A) x_mode A^T
  * (the residual of Alg. 4) when rows > 0, or E = X when rows == 0; A is a

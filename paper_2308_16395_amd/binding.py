@@ -46,7 +46,7 @@ STATUS_NAMES = {
 EXPORTED = ["st_create", "st_init", "st_update", "st_ranks", "st_core", "st_factor",
             "st_sv", "st_recon_error", "st_stats", "st_reconstruct_slice",
             "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile", "st_aux_v",
-            "st_tucker_workspace", "st_tucker_fwd", "st_tucker_bwd"]
+            "st_tucker_workspace", "st_tucker_fwd", "st_tucker_bwd", "st_ttm_noalloc"]
 ST_RECONSTRUCT, ST_PROJECT = 0, 1
 
 KERNEL_GROUPS = ["ttm1", "ttm", "gram", "eig", "ttm_ext", "isvd", "svd", "rot_v", "rot_c",
@@ -134,6 +134,9 @@ _sig = {
     "st_reconstruct_slice": (C.c_int, [_h, C.c_int64, C.c_void_p]),
     "st_ttm": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_void_p,
                          C.c_int64, C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "st_ttm_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_int32,
+                                 C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_double),
+                                 C.c_int32, C.c_void_p]),
     "st_gram": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_void_p,
                           C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
     "st_profile": (C.c_int, [_h, C.POINTER(st_kernel_profile), C.c_int32, C.c_int32]),
@@ -166,6 +169,7 @@ st_recon_error = lib.st_recon_error
 st_stats = lib.st_stats
 st_reconstruct_slice = lib.st_reconstruct_slice
 st_ttm = lib.st_ttm
+st_ttm_noalloc = lib.st_ttm_noalloc
 st_gram = lib.st_gram
 st_profile = lib.st_profile
 st_tucker_workspace = lib.st_tucker_workspace

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1611,8 +1612,14 @@ int st_reconstruct_slice(const st_handle *hc, int64_t t, float *out) {
   return h->do_reconstruct_slice(t, out);
 }
 
-int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
-           int64_t rows, float *out, double *norms, int32_t precision, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Shape checks shared by st_ttm and st_ttm_noalloc; fills the fibre layout.
+int ttm_args(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
+             int64_t rows, const float *out, const double *norms, int32_t precision,
+             FiberIn &in, Prec &pr) {
   if (!x || !dims || !a || !out || nmodes < 1 || nmodes > ST_MAX_MODES || mode < 0 ||
       mode >= nmodes || rows < 1 || precision < ST_FP32 || precision > ST_FP64)
     return ST_EINVAL;
@@ -1623,54 +1630,156 @@ int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, co
     if (k > mode) hi *= dims[k];
   }
   if (norms && rows > 384) return ST_EINVAL;
-  const int64_t nk = dims[mode];
-  hipStream_t s = (hipStream_t)stream;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;  // initialises the runtime
-  FiberIn in{};
+  in = FiberIn{};
   in.x = x;
   in.a = lo;
-  in.n = nk;
+  in.n = dims[mode];
   in.F = lo * hi;
+  pr = precision == ST_BF16X3 ? Prec::BF16X3 : (precision == ST_FP64 ? Prec::FP64 : Prec::FP32);
+  return ST_OK;
+}
+
+// Device buffers of one stateless TTM: the FP64 or split-bf16 copy of A (by
+// precision) and the partial and total residual norms (with norms only).
+struct TtmScratch {
+  double *a64 = nullptr;
+  __bf16 *bh = nullptr, *bl = nullptr;
+  double *part = nullptr, *sum = nullptr;
+};
+
+size_t ttm_scratch_bytes(const FiberIn &in, int64_t rows, Prec pr, bool norms, size_t *off) {
+  // offsets (256-byte aligned): [0] sum, [1] part, [2] a64 or bh, [3] bl
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int64_t ldb = round_up(in.n, 8);
+  size_t o = 0;
+  off[0] = o;
+  o += norms ? up(2 * sizeof(double)) : 0;
+  off[1] = o;
+  o += norms ? up(2 * (size_t)fiber_max_blocks(in.F) * sizeof(double)) : 0;
+  off[2] = o;
+  if (pr == Prec::FP64) o += up((size_t)rows * in.n * sizeof(double));
+  if (pr == Prec::BF16X3) o += up((size_t)rows * ldb * sizeof(__bf16));
+  off[3] = o;
+  if (pr == Prec::BF16X3) o += up((size_t)rows * ldb * sizeof(__bf16));
+  return o;
+}
+
+// The TTM itself on caller-provided scratch; waits for its work on s.
+hipError_t ttm_run(const FiberIn &in, const float *a, int64_t rows, float *out, double *norms,
+                   Prec pr, const TtmScratch &sc, hipStream_t s) {
   FiberW w{};
   w.w = a;
-  w.ldw = nk;
-  __bf16 *bh = nullptr, *bl = nullptr;
-  double *part = nullptr, *sum = nullptr, *a64 = nullptr;
-  const Prec pr = precision == ST_BF16X3 ? Prec::BF16X3
-                                         : (precision == ST_FP64 ? Prec::FP64 : Prec::FP32);
+  w.ldw = in.n;
   hipError_t e = hipSuccess;
   if (pr == Prec::FP64) {
-    e = hipMalloc((void **)&a64, rows * nk * sizeof(double));
-    if (e == hipSuccess) e = launch_f32_to_f64(a, rows * nk, a64, s);
-    w.w64 = a64;
+    e = launch_f32_to_f64(a, rows * in.n, sc.a64, s);
+    w.w64 = sc.a64;
   }
   if (pr == Prec::BF16X3) {
-    const int64_t ldb = round_up(nk, 8);
-    e = hipMalloc((void **)&bh, rows * ldb * sizeof(__bf16));
-    if (e == hipSuccess) e = hipMalloc((void **)&bl, rows * ldb * sizeof(__bf16));
-    if (e == hipSuccess) e = launch_split_rows(a, rows, nk, nk, bh, bl, ldb, s);
-    w.w_hi = bh;
-    w.w_lo = bl;
+    const int64_t ldb = round_up(in.n, 8);
+    e = launch_split_rows(a, rows, in.n, in.n, sc.bh, sc.bl, ldb, s);
+    w.w_hi = sc.bh;
+    w.w_lo = sc.bl;
     w.ldw_bf = ldb;
   }
   int nb = 0;
-  if (e == hipSuccess && norms) {
-    e = hipMalloc((void **)&part, 2 * (size_t)fiber_max_blocks(in.F) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&sum, 2 * sizeof(double));
-  }
   if (e == hipSuccess)
-    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, 0, lo, rows}, part, pr, s, &nb);
-  if (e == hipSuccess && norms) e = launch_reduce_pairs(part, nb, sum, s);
+    e = launch_fiber_project(in, w, 0, (int)rows, FiberOut{out, 0, in.a, rows},
+                             norms ? sc.part : nullptr, pr, s, &nb);
+  if (e == hipSuccess && norms) e = launch_reduce_pairs(sc.part, nb, sc.sum, s);
   if (e == hipSuccess && norms)
-    e = hipMemcpyAsync(norms, sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(norms, sc.sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (bh) (void)hipFree(bh);
-  if (bl) (void)hipFree(bl);
-  if (a64) (void)hipFree(a64);
-  if (part) (void)hipFree(part);
-  if (sum) (void)hipFree(sum);
+  return e;
+}
+
+// Fixed device scratch of st_ttm_noalloc (each GPU the library runs on holds
+// its own copy until the process ends). Host code never uses this name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int st_ttm(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
+           int64_t rows, float *out, double *norms, int32_t precision, void *stream) {
+  FiberIn in{};
+  Prec pr;
+  int rc = ttm_args(x, nmodes, dims, mode, a, rows, out, norms, precision, in, pr);
+  if (rc != ST_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;  // initialises the runtime
+  size_t off[4];
+  const size_t bytes = ttm_scratch_bytes(in, rows, pr, norms != nullptr, off);
+  unsigned char *buf = nullptr;
+  hipError_t e = bytes ? hipMalloc((void **)&buf, bytes) : hipSuccess;
+  if (e == hipSuccess) {
+    TtmScratch sc;
+    sc.sum = reinterpret_cast<double *>(buf + off[0]);
+    sc.part = reinterpret_cast<double *>(buf + off[1]);
+    sc.a64 = reinterpret_cast<double *>(buf + off[2]);
+    sc.bh = reinterpret_cast<__bf16 *>(buf + off[2]);
+    sc.bl = reinterpret_cast<__bf16 *>(buf + off[3]);
+    e = ttm_run(in, a, rows, out, norms, pr, sc, s);
+  }
+  if (buf) (void)hipFree(buf);
   if (e == hipErrorOutOfMemory) return ST_ENOMEM;
+  return e == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_ttm_noalloc(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode,
+                   const float *a, int64_t rows, float *out, double *norms, int32_t precision,
+                   void *stream) {
+  FiberIn in{};
+  Prec pr;
+  int rc = ttm_args(x, nmodes, dims, mode, a, rows, out, norms, precision, in, pr);
+  if (rc != ST_OK) {
+    set_stateless_error("st_ttm_noalloc: invalid arguments");
+    return rc;
+  }
+  size_t off[4];
+  const size_t bytes = ttm_scratch_bytes(in, rows, pr, norms != nullptr, off);
+  if (bytes > kNoAllocScratchBytes) {
+    set_stateless_error("st_ttm_noalloc: the call needs more scratch than the fixed 8 MiB "
+                        "(fibre count or rows x dims[mode] too large)");
+    return ST_EINVAL;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;
+  void *base = nullptr;
+  if (scratch_address(dev, &base) != hipSuccess) {
+    set_stateless_error("st_ttm_noalloc: no device address for the scratch array");
+    return ST_EHIP;
+  }
+  unsigned char *buf = static_cast<unsigned char *>(base);
+  TtmScratch sc;
+  sc.sum = reinterpret_cast<double *>(buf + off[0]);
+  sc.part = reinterpret_cast<double *>(buf + off[1]);
+  sc.a64 = reinterpret_cast<double *>(buf + off[2]);
+  sc.bh = reinterpret_cast<__bf16 *>(buf + off[2]);
+  sc.bl = reinterpret_cast<__bf16 *>(buf + off[3]);
+  const hipError_t e = ttm_run(in, a, rows, out, norms, pr, sc, (hipStream_t)stream);
   return e == hipSuccess ? ST_OK : ST_EHIP;
 }
 
