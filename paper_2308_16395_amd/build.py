@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstucker.so")
 SOURCES = ["k_fiber_ff.hip", "k_fiber_fd.hip", "k_fiber_dd.hip", "k_gram.hip", "k_rot.hip",
-           "k_isvd.hip", "engine.hip", "tucker_ops.hip"]
+           "k_isvd.hip", "k_ttm.hip", "engine.hip", "tucker_ops.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
@@ -44,7 +44,7 @@ def compile_flags():
 # k_gram.hip with the VGPR form.)
 _VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 SOURCE_FLAGS = {src: _VGPR_FORM for src in
-                ("k_rot.hip", "k_fiber_ff.hip", "k_fiber_fd.hip", "k_fiber_dd.hip")}
+                ("k_rot.hip", "k_fiber_ff.hip", "k_fiber_fd.hip", "k_fiber_dd.hip", "k_ttm.hip")}
 
 
 def _compile(src):

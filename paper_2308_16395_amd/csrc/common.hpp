@@ -166,6 +166,15 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
                                 const FiberOut &out, double *resid_partials, Prec prec,
                                 hipStream_t s, int *nparts = nullptr);
 
+// The contiguous-fibre special case of launch_fiber_project (FP32 slice,
+// a == 1, all rows from 0, n <= 128, n % 4 == 0, at most 64 rows, FP32 or
+// split-bf16 products): a persistent kernel that streams 64-fibre tiles
+// through LDS. launch_fiber_project takes it whenever it is eligible.
+bool ttm_contig_eligible(const FiberIn &in, int m0, int mcount, const FiberOut &out, Prec prec,
+                         bool resid);
+hipError_t launch_ttm_contig(const FiberIn &in, const FiberW &w, int mcount, const FiberOut &out,
+                             double *partials, Prec prec, hipStream_t s, int *nparts);
+
 // Mode-d rotation (MAPPED input) with FP64 products and sums:
 // P[f][m] = sum_k X'[f][k] W[m][k] (W row-major, ld ldw), X'[f][k] = X[f][k]
 // for k < n; element n: none (extra_mode 0), extra[f] (1), or

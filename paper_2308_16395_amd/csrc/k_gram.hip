@@ -437,6 +437,8 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
   if (prec == Prec::BF16X3 && (w.w_hi == nullptr || w.w_lo == nullptr))
     return hipErrorInvalidValue;
   if (prec == Prec::FP32 && w.w == nullptr) return hipErrorInvalidValue;
+  if (ttm_contig_eligible(in, m0, mcount, out, prec, resid_partials != nullptr))
+    return launch_ttm_contig(in, w, mcount, out, resid_partials, prec, s, nparts);
   if (!in.x64 && !out.o64)
     return launch_fiber_ff(in, w, m0, mcount, out, resid_partials, prec, s, nparts);
   if (!in.x64 && out.o64)

@@ -37,6 +37,13 @@ CASES = [
     ((12, 300), 1, 260),
     ((320, 6, 2), 0, 300),   # fused residual with more than 256 rows (20 tiles)
     ((24, 380), 1, 370),     # 24 tiles
+    # contiguous FP32 fibres with n <= 128, n % 4 == 0 (the persistent tile kernel)
+    ((128, 128, 16), 0, 39),  # the mode-1 shape of the 128^3 x 16 stream, 32 tiles
+    ((96, 37, 3), 0, 17),     # ragged last tile (111 fibres)
+    ((36, 50), 0, 64),        # n padded to 64 inside the kernel, rows clipped to 36
+    ((64, 129), 0, 7),        # one fibre in the last tile
+    ((4, 70), 0, 3),          # shortest fibre
+    ((128, 40000), 0, 64),    # more tiles than blocks (persistent loop), 4 row tiles
 ]
 
 
@@ -123,3 +130,20 @@ def test_gram_rejects_fibres_longer_than_512():
     xd = torch.zeros(520 * 3, device="cuda")
     with pytest.raises(StError):
         gram(xd, dims, 0, None, precision="fp64")
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp32", 2e-5), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("dims,rows", [((128, 300), 39), ((36, 50), 20)])
+def test_contiguous_projection_without_norms(dims, rows, precision, rtol):
+    """The projection alone (no residual) on contiguous fibres."""
+    import torch
+
+    from paper_2308_16395_amd.binding import ttm
+
+    x, u = _case(dims, 0, rows, 5 + rows)
+    xd = torch.from_numpy(np.ascontiguousarray(x.ravel(order="F"))).cuda()
+    a = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()
+    out = ttm(xd, dims, 0, a, precision=precision, norms=False)
+    y_ref, _, _ = _ref(x, u.T, 0)
+    got = out.cpu().numpy().astype(np.float64).reshape([rows] + list(dims[1:]), order="F")
+    assert np.linalg.norm(got - y_ref) <= rtol * np.linalg.norm(y_ref)
