@@ -79,7 +79,7 @@ typedef struct st_config {
                                   above (1 - g) eps, or whose ISVD residual q
                                   (Alg. 3) lies above (1 - g) eps, has its
                                   decisions and state changes redone from FP64
-                                  products; 0 = default (3e-2 FP32, 1.5e-1
+                                  products; 0 = default (1e-2 FP32, 5e-2
                                   bf16x3); unused by ST_FP64 */
   int64_t max_rank_d;          /* cap on the streaming rank r_d; 0 = no cap */
   void *stream;                /* hipStream_t (of this library's HIP runtime) to
@@ -152,6 +152,10 @@ typedef struct st_slice_stats {
   int32_t refined_gram;               /* residual Grams redone with FP64 products
                                          because a tail sum of Alg. 1 fell in the
                                          guard band of eps^2 */
+  double e_norm_fast[ST_MAX_MODES];   /* ||E_k|| from the form's own products at the
+                                         current ranks, before any refinement */
+  double q_fast;                      /* q from the form's own products, before any
+                                         refinement */
 } st_slice_stats;
 
 typedef struct st_handle st_handle;

@@ -95,6 +95,8 @@ class st_slice_stats(C.Structure):
         ("refined_modes", C.c_int32),
         ("refined_isvd", C.c_int32),
         ("refined_gram", C.c_int32),
+        ("e_norm_fast", C.c_double * ST_MAX_MODES),
+        ("q_fast", C.c_double),
     ]
 
 
@@ -388,7 +390,8 @@ class StreamingTucker:
                     guard_hits=s.guard_hits, orth_check=s.orth_check, delta2=s.delta2,
                     ms_total=s.ms_total, ms_modes=s.ms_modes, ms_isvd=s.ms_isvd,
                     refined_modes=bool(s.refined_modes), refined_isvd=bool(s.refined_isvd),
-                    refined_gram=s.refined_gram)
+                    refined_gram=s.refined_gram,
+                    e_norm_fast=[s.e_norm_fast[k] for k in range(m)], q_fast=s.q_fast)
 
     def profile(self, reset=False):
         """Per kernel group: launches, device ms, algorithmic flops and bytes."""

@@ -268,7 +268,8 @@ struct WaveRed {
 // close -- and the ordered lists of active and deflated indices by ballot
 // prefix sums. zz is summed in the block's fixed order.
 __global__ __launch_bounds__(256) void sec_prep_kernel(SecData s, const double *S, const double *p,
-                                                       double q, int grow, double tol) {
+                                                       double q, const double *qsq, int grow,
+                                                       double tol) {
   __shared__ int close_pair;
   __shared__ int wcount[2][4];
   __shared__ double red[16];
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(256) void sec_prep_kernel(SecData s, const double *
   for (int t = tid; t <= r; t += blockDim.x) {
     if (t == 0) {
       s.d[0] = 0.0;
-      s.z[0] = grow ? q : 0.0;
+      s.z[0] = grow ? (qsq ? sqrt(qsq[0]) : q) : 0.0;
       s.active[0] = grow ? 1 : 0;
     } else {
       const double z = p[r - t];
@@ -398,11 +399,11 @@ __global__ __launch_bounds__(64) void sec_vec_kernel(SecData s, int ntrip, doubl
   if (lane == 0) Snew[col] = sigma;
 }
 
-hipError_t launch_secular_svd(SecData s, const double *S, const double *p, double q, int grow,
-                              double tol, int ntrip, double *U2, double *V2, double *Snew,
-                              hipStream_t st) {
+hipError_t launch_secular_svd(SecData s, const double *S, const double *p, double q,
+                              const double *qsq, int grow, double tol, int ntrip, double *U2,
+                              double *V2, double *Snew, hipStream_t st) {
   const int n = s.n;
-  hipLaunchKernelGGL(sec_prep_kernel, dim3(1), dim3(256), 0, st, s, S, p, q, grow, tol);
+  hipLaunchKernelGGL(sec_prep_kernel, dim3(1), dim3(256), 0, st, s, S, p, q, qsq, grow, tol);
   hipLaunchKernelGGL(sec_roots_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   hipLaunchKernelGGL(sec_zhat_kernel, dim3((n + 3) / 4), dim3(256), 0, st, s);
   const size_t lds = 2 * (size_t)n * sizeof(double);
@@ -1084,38 +1085,69 @@ hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const doub
 }
 
 // Gn ((r + 1) x (r + 1)) = [[G0, g / q], [g^T / q, ee / q^2]] after appending
-// v = e / q to V0 (g = V0^T e, ee = ||e||^2); or Gn = G0 (grow = 0).
+// v = e / q to V0 (g = V0^T e, ee = ||e||^2, q = sqrt(ee) read on the device, so
+// the appended column has unit norm whatever q decided the growth); or Gn = G0
+// (grow = 0).
 __global__ void g0_update_kernel(const double *G0, int r, const double *g, const double *ee,
-                                 double inv_q, int grow, double *Gn) {
+                                 int grow, double *Gn) {
   const int c = r + grow;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= c * c) return;
   const int i = idx % c, j = idx / c;
   double v;
-  if (i < r && j < r) v = G0[i + (size_t)r * j];
-  else if (i < r) v = g[i] * inv_q;
-  else if (j < r) v = g[j] * inv_q;
-  else v = ee[0] * inv_q * inv_q;
+  if (i < r && j < r) {
+    v = G0[i + (size_t)r * j];
+  } else {
+    const double inv_q = 1.0 / sqrt(ee[0]);
+    if (i < r) v = g[i] * inv_q;
+    else if (j < r) v = g[j] * inv_q;
+    else v = ee[0] * inv_q * inv_q;
+  }
   Gn[i + (size_t)c * j] = v;
 }
 
-hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
-                            double inv_q, int grow, double *Gn, hipStream_t s) {
+hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee, int grow,
+                            double *Gn, hipStream_t s) {
   const int c = r + grow;
   if (c <= 0) return hipSuccess;
   hipLaunchKernelGGL(g0_update_kernel, dim3((unsigned)((c * c + 255) / 256)), dim3(256), 0, s,
-                     G0, r, g, ee, inv_q, grow, Gn);
+                     G0, r, g, ee, grow, Gn);
   return hipGetLastError();
 }
 
-__global__ void scale_kernel(double *x, int64_t n, double a) {
+// out[i] = sum_b part[b * n + i] (b < nb), one thread per entry, in a fixed
+// order: four interleaved partial sums, then their pairwise sum.
+__global__ void batch_sum_kernel(const double *part, int nb, int64_t n, double *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] *= a;
+  if (i >= n) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int b = 0;
+  for (; b + 4 <= nb; b += 4) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] += part[(size_t)(b + c) * n + i];
+  }
+  for (int c = 0; b < nb; ++b, ++c) a[c] += part[(size_t)b * n + i];
+  out[i] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
-hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s) {
+hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, a);
+  if (nb < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                     nb, n, out);
+  return hipGetLastError();
+}
+
+// x /= sqrt(ss[0]) (ss on the device: a sum of squares formed by an earlier launch)
+__global__ void scale_rsqrt_kernel(double *x, int64_t n, const double *ss) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= 1.0 / sqrt(ss[0]);
+}
+
+hipError_t launch_scale_rsqrt(double *x, int64_t n, const double *ss, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_rsqrt_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
+                     ss);
   return hipGetLastError();
 }
 

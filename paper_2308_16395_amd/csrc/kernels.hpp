@@ -25,9 +25,10 @@ hipError_t launch_gather3(double *dst, const double *a, int na, int oa, const do
 hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s);
 hipError_t launch_colsum(const double *part, int nb, int r, double *out, const double *add,
                          double *out2, const double *q2part, double *q2, hipStream_t s);
-hipError_t launch_secular_svd(SecData s, const double *S, const double *p, double q, int grow,
-                              double tol, int ntrip, double *U2, double *V2, double *Snew,
-                              hipStream_t st);
+// q enters S' as given, or as sqrt(*qsq) read on the device when qsq is not null
+hipError_t launch_secular_svd(SecData s, const double *S, const double *p, double q,
+                              const double *qsq, int grow, double tol, int ntrip, double *U2,
+                              double *V2, double *Snew, hipStream_t st);
 hipError_t launch_ud_update(const double *Ud, int64_t ldo, int64_t nd, int r, const double *U2,
                             int c, double *Un, int64_t ldn, hipStream_t s);
 hipError_t launch_build_rot_w(const double *U2, const double *V2, int r, int c, int kv,
@@ -90,9 +91,11 @@ hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const doub
                             const double *dd, int given, double *p1, double *w1, double *t2,
                             double *p2, double *w2, double *p, double *ws, double *sc,
                             double *g, double *ge, hipStream_t s);
-hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee,
-                            double inv_q, int grow, double *Gn, hipStream_t s);
-hipError_t launch_scale(double *x, int64_t n, double a, hipStream_t s);
+hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee, int grow,
+                            double *Gn, hipStream_t s);
+hipError_t launch_scale_rsqrt(double *x, int64_t n, const double *ss, hipStream_t s);
+// out[i] = sum over b < nb of part[b * n + i], in a fixed order
+hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, hipStream_t s);
 // delta = a - b (n rows) and per-block pairs (sum b * delta, sum delta^2) in
 // part[2 * nblocks] (reduce with launch_reduce_pairs).
 hipError_t launch_delta(const double *a, const double *b, int64_t n, double *delta, double *part,

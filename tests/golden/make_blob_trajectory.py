@@ -59,6 +59,8 @@ def main():
 
     orc = StreamingTucker(np.stack([sl(t) for t in range(n_init)], axis=-1), tau,
                           core_update=core_update)
+    vm = orc.vmat()
+    init_v_orth = float(np.max(np.abs(vm.T @ vm - np.eye(vm.shape[1]))))
     out = dict(
         source="FP64 oracle (oracle/tucker.py), blob stream config 1, float32 slice values",
         core_update=core_update,
@@ -86,6 +88,11 @@ def main():
         print(t, orc.ranks, f"{time.time() - t0:.0f}s", flush=True)
     name = ("blobs128_oracle_trajectory.json" if core_update == "literal"
             else f"blobs128_oracle_trajectory_{core_update}.json")
+    # how far the auxiliary V of the core factorization is from orthonormal
+    # (the Gram-based SVD of Alg. 1 leaves about u (s_1 / s_r)^2)
+    vm = orc.vmat()
+    out["final_v_orth"] = float(np.max(np.abs(vm.T @ vm - np.eye(vm.shape[1]))))
+    out["init_v_orth"] = init_v_orth
     with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f)
 
