@@ -9,7 +9,10 @@ of element positions (with the data there), as the blob-stream script does.
 A full 1000-slice oracle run does not fit a test; the first updates carry the
 initial growth of every mode.
 
-Usage: python tests/golden/make_fourier_trajectory.py [n_updates]
+With the second argument ``factored`` the oracle keeps the core as C = V x_d S
+and the output goes to a second file (same decisions, different probes).
+
+Usage: python tests/golden/make_fourier_trajectory.py [n_updates] [literal|factored]
 """
 
 import json
@@ -31,6 +34,7 @@ from synth import CONFIGS, make_stream  # noqa: E402
 
 def main():
     n_updates = int(sys.argv[1]) if len(sys.argv) > 1 else 40
+    core_update = sys.argv[2] if len(sys.argv) > 2 else "literal"
     cfg = CONFIGS[4]
     s = make_stream(4)
     n_init, tau = cfg["n_init"], cfg["eps"]
@@ -45,12 +49,15 @@ def main():
     x0 = np.empty(s.dims + (n_init,), dtype=np.float64, order="F")
     for t in range(n_init):
         x0[..., t] = flat32(t).reshape(s.dims, order="F")
-    orc = StreamingTucker(x0, tau)
+    orc = StreamingTucker(x0, tau, core_update=core_update)
     del x0
-    print("init", orc.ranks, f"{time.time() - t0:.0f}s", flush=True)
+    vm = orc.vmat()
+    init_v_orth = float(np.max(np.abs(vm.T @ vm - np.eye(vm.shape[1]))))
+    print("init", orc.ranks, f"{time.time() - t0:.0f}s", init_v_orth, flush=True)
     out = dict(
         source="FP64 oracle (oracle/tucker.py), random-Fourier stream config 4, float32 "
                "slice values",
+        core_update=core_update,
         stream=dict(dims=list(s.dims), n_init=n_init, tau=tau, n_slices=n_slices,
                     seed=cfg["seed"]),
         init_ranks=list(orc.ranks), init_bound=orc.recon_error_bound(), slices=[],
@@ -71,7 +78,14 @@ def main():
                                    data=d[pos].tolist(), slice_norm=float(np.linalg.norm(d))))
             out["checkpoints"].append(dict(after=t, probes=probes))
         print(t, orc.ranks, f"{time.time() - t0:.0f}s", flush=True)
-    with open(os.path.join(HERE, "fourier512_oracle_trajectory.json"), "w") as f:
+    name = ("fourier512_oracle_trajectory.json" if core_update == "literal"
+            else f"fourier512_oracle_trajectory_{core_update}.json")
+    # how far the auxiliary V of the core factorization is from orthonormal
+    # (the Gram-based SVD of Alg. 1 leaves about u (s_1 / s_r)^2)
+    vm = orc.vmat()
+    out["final_v_orth"] = float(np.max(np.abs(vm.T @ vm - np.eye(vm.shape[1]))))
+    out["init_v_orth"] = init_v_orth
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f)
 
 

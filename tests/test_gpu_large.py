@@ -1,28 +1,76 @@
 """GPU on the 512 x 512 x 256 random-Fourier stream (tau = 1e-4): the
 workload with the longest fibres (n = 512, so the FP64 Gram of the initial
 decomposition runs over row-chunk pairs) and ranks near 128 in every spatial
-mode.
+mode, in the FP32 and bf16x3 forms and both core updates.
 
-The oracle cannot run at this size inside a test, so the checks are properties
-that hold at any size: the certified bound and the true error of the stored
-slices are within tau after init and after each form's updates, the spatial
-factors and V are orthonormal, S is positive and sorted, the FP32 and bf16x3
-forms agree on the spatial ranks, and the factored core equals V x_d S.
+The oracle's decisions on the first 40 updates, and its reconstructions of
+probe slices at two checkpoints (at a seeded sample of element positions), were
+recorded by tests/golden/make_fourier_trajectory.py (oracle only). Every form
+must reproduce the oracle's ranks after every update and its reconstructions
+element by element on the sample within 1e-5 (FP32) / 1e-4 (bf16x3) of the
+slice norm. Properties that hold at any size are checked on the final state:
+the certified bound (equal to the oracle's, up to the rounding of the bf16x3
+products in the residual norms it sums) and the true error of the probe slices
+are within tau, the
+spatial factors are orthonormal, S is positive and sorted, V is as close to
+orthonormal as the oracle's own V (the Gram-based SVD of Alg. 1 leaves about
+u (s_1 / s_r)^2 in both), and the factored core equals V x_d S.
 """
 
+import json
 import math
+import os
 
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
-N_INIT, N_UPD, TAU = 20, 10, 1e-4
+HERE = os.path.dirname(__file__)
+GOLDEN = {"literal": os.path.join(HERE, "golden", "fourier512_oracle_trajectory.json"),
+          "factored": os.path.join(HERE, "golden", "fourier512_oracle_trajectory_factored.json")}
 
 
 def _stream():
     from synth import make_stream
 
     return make_stream(4)
+
+
+def _load(core_update):
+    with open(GOLDEN[core_update]) as f:
+        return json.load(f)
+
+
+def _run(precision, core_update, golden):
+    import torch
+
+    import paper_2308_16395_amd as pkg
+
+    s = _stream()
+    dev = torch.device("cuda:0")
+    n_init, tau = golden["stream"]["n_init"], golden["stream"]["tau"]
+    n = golden["stream"]["n_slices"]
+    x0 = torch.cat([s.slice_torch(t, dev, torch.float32) for t in range(n_init)])
+    st = pkg.StreamingTucker(s.dims, tau, precision=precision, core_update=core_update)
+    st.init(x0, n_init)
+    del x0
+    assert list(st.ranks) == golden["init_ranks"]
+    assert st.recon_error()[0] <= tau
+    pos = torch.tensor(golden["probe_positions"], dtype=torch.long, device=dev)
+    cks = {ck["after"]: ck for ck in golden["checkpoints"]}
+    traj, probe_err = [], {}
+    for t in range(n_init, n):
+        st.update(s.slice_torch(t, dev, torch.float32))
+        traj.append(tuple(st.ranks))
+        if t in cks:
+            worst = 0.0
+            for pr in cks[t]["probes"]:
+                g = st.reconstruct_slice(pr["t"])[pos].double().cpu().numpy()
+                o = np.asarray(pr["recon"])
+                worst = max(worst, float(np.linalg.norm(g - o) / np.linalg.norm(pr["data"])))
+            probe_err[t] = worst
+    return st, s, traj, probe_err
 
 
 def _true_error(st, s, ts):
@@ -37,53 +85,57 @@ def _true_error(st, s, ts):
     return math.sqrt(err2 / nrm2)
 
 
-def _run(precision, core_update):
+FORMS = [("fp32", "literal", 1e-5), ("fp32", "factored", 1e-5), ("bf16x3", "literal", 1e-4),
+         ("bf16x3", "factored", 1e-4)]
+
+
+@pytest.mark.parametrize("precision,core_update,err_tol", FORMS,
+                         ids=[f"{p}-{c}" for p, c, _ in FORMS])
+def test_fourier_512_stream_against_oracle(precision, core_update, err_tol):
     import torch
 
-    import paper_2308_16395_amd as pkg
-
-    s = _stream()
-    dev = torch.device("cuda:0")
-    x0 = torch.cat([s.slice_torch(t, dev, torch.float32) for t in range(N_INIT)])
-    st = pkg.StreamingTucker(s.dims, TAU, precision=precision, core_update=core_update)
-    st.init(x0, N_INIT)
-    del x0
-    assert st.recon_error()[0] <= TAU
-    for t in range(N_INIT, N_INIT + N_UPD):
-        st.update(s.slice_torch(t, dev, torch.float32))
-    return st, s
-
-
-@pytest.mark.parametrize("precision,core_update",
-                         [("fp32", "factored"), ("bf16x3", "factored"), ("fp32", "literal")])
-def test_fourier_512_stream_meets_tau(precision, core_update):
-    import torch
-
-    st, s = _run(precision, core_update)
+    if not os.path.exists(GOLDEN[core_update]):
+        pytest.skip("oracle trajectory not generated")
+    golden = _load(core_update)
+    st, s, traj, probe_err = _run(precision, core_update, golden)
+    ref = [tuple(x["ranks"]) for x in golden["slices"]]
+    assert len(traj) == len(ref)
+    for i, (a, b) in enumerate(zip(traj, ref)):
+        g = golden["slices"][i]
+        assert a == b, (golden["stream"]["n_init"] + i, a, b, g["q_over_eps"], g["e_over_eps"])
+    assert probe_err and max(probe_err.values()) <= err_tol, probe_err
+    tau = golden["stream"]["tau"]
     bound, _ = st.recon_error()
-    assert bound <= TAU
-    ts = [0, 7, N_INIT - 1, N_INIT, N_INIT + N_UPD - 1]
-    assert _true_error(st, s, ts) <= TAU
-    ranks = st.ranks
-    assert all(60 <= r <= n for r, n in zip(ranks[:3], s.dims))
+    ob = golden["slices"][-1]["bound"]
+    assert bound <= tau
+    if precision == "bf16x3":
+        # Each residual norm of Alg. 4 measured with bf16x3 products carries their
+        # rounding (about 5e-6 of the slice norm, from the 2^-24 split of every
+        # operand accumulated over n = 512), which adds in quadrature to every
+        # mode's term of the bound: allow (1e-5)^2 per slice mode on top of the
+        # oracle's bound^2, and nothing below it beyond 1%.
+        assert ob * (1 - 1e-2) <= bound
+        assert bound ** 2 - ob ** 2 <= 3 * (1e-5) ** 2, (bound, ob)
+    else:
+        np.testing.assert_allclose(bound, ob, rtol=1e-3)
+    n_init, n = golden["stream"]["n_init"], golden["stream"]["n_slices"]
+    assert _true_error(st, s, [0, n_init // 2, n_init - 1, n_init, n - 1]) <= tau
     for k in range(3):
         u = st.factor(k)
-        g = u.T @ u
-        assert torch.max(torch.abs(g - torch.eye(g.shape[0], device=g.device, dtype=g.dtype))) < 1e-6
+        gm = u.T @ u
+        assert torch.max(torch.abs(gm - torch.eye(gm.shape[0], device=gm.device,
+                                                  dtype=gm.dtype))) < 1e-6
     sv = st.sv()
     assert all(x > 0 for x in sv) and all(a >= b for a, b in zip(sv, sv[1:]))
+    v = st.aux_v()
+    gv = v.T @ v
+    v_orth = torch.max(torch.abs(gv - torch.eye(gv.shape[0], device=gv.device,
+                                                dtype=gv.dtype))).item()
+    assert v_orth <= 10.0 * golden["final_v_orth"] + 1e-12, (v_orth, golden["final_v_orth"])
     if core_update == "factored":
-        # V from the Gram-based initial SVD (Alg. 1) is orthonormal to about
-        # u (s_1 / s_r)^2: the tail rule may keep a last singular value far
-        # below eps, as it does on this stream
-        v = st.aux_v()
-        gv = v.T @ v
-        tol = max(1e-6, 64 * 2.0 ** -52 * (sv[0] / sv[-1]) ** 2)
-        assert torch.max(torch.abs(gv - torch.eye(gv.shape[0], device=gv.device,
-                                                  dtype=gv.dtype))).item() < tol
         # C = V x_d S: column j of the mode-d unfolding transposed is S_j V(:, j)
         core = st.core().double()
         svt = torch.tensor(sv, device=v.device, dtype=v.dtype)
-        ref = (v * svt[None, :]).T.contiguous().reshape(-1)
-        assert torch.max(torch.abs(core - ref)).item() <= 1e-5 * torch.max(torch.abs(ref)).item()
+        cref = (v * svt[None, :]).T.contiguous().reshape(-1)
+        assert torch.max(torch.abs(core - cref)).item() <= 1e-5 * torch.max(torch.abs(cref)).item()
     st.close()
