@@ -510,7 +510,8 @@ def main():
         whole = {g: {k: prof_untimed[g][k] + prof[g][k] for k in prof[g]} for g in prof}
         info = dict(value=round(args.steps / dt, 3), ms_per_step=round(1e3 * dt / args.steps, 4),
                     init_s=round(init_s, 3), ranks_final=list(st.ranks),
-                    recon_error_bound=st.recon_error()[0], guard_hits_untimed=guard)
+                    recon_error_bound=st.recon_error()[0], guard_hits_untimed=guard,
+                    qr_fixes=st.stats()["qr_total"])
         if golden is not None:
             ref = [tuple(x["ranks"]) for x in golden["slices"]][:len(traj)]
             bad = [n_init + i for i, (a, b) in enumerate(zip(traj, ref)) if tuple(a) != b]

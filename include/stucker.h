@@ -73,7 +73,8 @@ typedef struct st_config {
   int64_t dims[ST_MAX_MODES];  /* n_1 .. n_{d-1}, each >= 1 */
   double tau;                  /* relative error tolerance (the paper's tau), > 0 */
   int32_t precision;           /* enum st_precision */
-  double orth_tol;             /* eps_m of the ISVD orthogonality check; 0 = 1e-5 */
+  double orth_tol;             /* eps_m of the orthogonality check of Alg. 3 on the new
+                                  direction (QR fix when exceeded); 0 = 1e-12 */
   double guard_rel;            /* relative guard band g of the reduced-precision
                                   forms (R9): a slice whose ||E_k|| (Alg. 4) lies
                                   above (1 - g) eps, or whose ISVD residual q
@@ -114,7 +115,9 @@ enum st_kernel_group {
   ST_K_UD = 9,        /* U~_d update */
   ST_K_REFINE = 10,   /* FP64-product coordinates of a slice and the ISVD correction
                          sweep (reduced-precision forms, guard band) */
-  ST_K_GROUPS = 11
+  ST_K_ORTH = 11,     /* Alg. 3's orthogonality check on the new v (growing slices)
+                         and its QR fix when the check fires */
+  ST_K_GROUPS = 12
 };
 
 /* Accumulated timing of one kernel group since the last reset: launches, total
@@ -135,10 +138,12 @@ typedef struct st_slice_stats {
   int32_t grew[ST_MAX_MODES];         /* new columns r'_k added to U_k */
   double q;                           /* ||e|| of Alg. 3 */
   int32_t isvd_ignored;               /* 1 if q <= eps (e ignored) */
-  int32_t qr_fired;                   /* 1 if the orthogonality check fired */
+  int32_t qr_fired;                   /* 1 if the orthogonality check of Alg. 3 fired on
+                                         this (growing) slice and its QR fix was applied */
   int32_t guard_hits;                 /* threshold tests re-evaluated with FP64
                                          products (sum of the three refinements) */
-  double orth_check;                  /* max_j |V(:,j)^T v| before any QR fix */
+  double orth_check;                  /* max_j |V(:,j)^T v| over all columns of V, v the
+                                         new unit direction (growing slices; else 0) */
   double delta2;                      /* squared error this slice adds to the bound */
   double ms_total;                    /* wall time of the call, ms */
   double ms_modes;                    /* non-streaming modes (Alg. 4), ms */
@@ -156,6 +161,7 @@ typedef struct st_slice_stats {
                                          current ranks, before any refinement */
   double q_fast;                      /* q from the form's own products, before any
                                          refinement */
+  int64_t qr_total;                   /* QR fixes of Alg. 3 applied since st_init */
 } st_slice_stats;
 
 typedef struct st_handle st_handle;

@@ -179,6 +179,7 @@ def isvd(u, s, v, b, eps, eps_m=1e-12, cgs2=True):
         p = p + p2
     q = float(np.linalg.norm(e))
     fired = False
+    orth = 0.0
     if q <= eps:
         s_prime = np.vstack([np.diag(s), p[None, :]])
         v_prime = v
@@ -189,7 +190,8 @@ def isvd(u, s, v, b, eps, eps_m=1e-12, cgs2=True):
         s_prime[r, :r] = p
         s_prime[r, r] = q
         v_prime = np.hstack([v, vnew[:, None]])
-        if r > 0 and np.max(np.abs(v.T @ vnew)) > eps_m:
+        orth = float(np.max(np.abs(v.T @ vnew))) if r > 0 else 0.0
+        if r > 0 and orth > eps_m:
             fired = True
             qm, rm = np.linalg.qr(v_prime)
             v_prime = qm
@@ -199,7 +201,8 @@ def isvd(u, s, v, b, eps, eps_m=1e-12, cgs2=True):
     v2 = v2t.T
     u_new = np.vstack([u @ u2[:r, :], u2[r:r + 1, :]])
     v_new = v_prime @ v2
-    info = dict(p=p, q=q, ignored=q <= eps, qr=fired, u2=u2, v2=v2, orth_single_pass=single)
+    info = dict(p=p, q=q, ignored=q <= eps, qr=fired, u2=u2, v2=v2, orth_single_pass=single,
+                orth_check=orth)
     return u_new, s_new, v_new, info
 
 
@@ -361,6 +364,7 @@ class StreamingTucker:
         self.xnorm2 += ynorm * ynorm
         self.disc += delta2
         rec.update(q=info["q"], ignored=bool(info["ignored"]), qr=info["qr"],
-                   orth_single_pass=info["orth_single_pass"], delta2=delta2, ranks=self.ranks)
+                   orth_single_pass=info["orth_single_pass"], orth_check=info["orth_check"],
+                   delta2=delta2, ranks=self.ranks)
         self.history.append(rec)
         return rec

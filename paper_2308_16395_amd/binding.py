@@ -50,7 +50,7 @@ EXPORTED = ["st_create", "st_init", "st_update", "st_ranks", "st_core", "st_fact
 ST_RECONSTRUCT, ST_PROJECT = 0, 1
 
 KERNEL_GROUPS = ["ttm1", "ttm", "gram", "eig", "ttm_ext", "isvd", "svd", "rot_v", "rot_c",
-                 "ud", "refine"]
+                 "ud", "refine", "orth"]
 
 
 class st_config(C.Structure):
@@ -97,6 +97,7 @@ class st_slice_stats(C.Structure):
         ("refined_gram", C.c_int32),
         ("e_norm_fast", C.c_double * ST_MAX_MODES),
         ("q_fast", C.c_double),
+        ("qr_total", C.c_int64),
     ]
 
 
@@ -391,7 +392,8 @@ class StreamingTucker:
                     ms_total=s.ms_total, ms_modes=s.ms_modes, ms_isvd=s.ms_isvd,
                     refined_modes=bool(s.refined_modes), refined_isvd=bool(s.refined_isvd),
                     refined_gram=s.refined_gram,
-                    e_norm_fast=[s.e_norm_fast[k] for k in range(m)], q_fast=s.q_fast)
+                    e_norm_fast=[s.e_norm_fast[k] for k in range(m)], q_fast=s.q_fast,
+                    qr_total=s.qr_total)
 
     def profile(self, reset=False):
         """Per kernel group: launches, device ms, algorithmic flops and bytes."""

@@ -96,7 +96,8 @@ struct st_handle {
   int64_t NY = 0;
   double tau = 0.0;
   Prec prec = Prec::FP32;
-  double orth_tol = 1e-5;
+  double orth_tol = 1e-12;
+  int64_t qr_total = 0;  // QR fixes applied since init
   double guard_rel = 0.0;
   int64_t max_rank_d = 0;
   hipStream_t stream = nullptr;
@@ -133,7 +134,8 @@ struct st_handle {
   // Mf[cur] holds M (r_d x r_d, ld r_d)
   int v0cur = 0;
   DBuf<double> Mf[2], Gf[2];  // M and G0 = V0^T V0 (r_d x r_d)
-  DBuf<double> tvec, wvec, e1buf, tmp64;
+  DBuf<double> tvec, wvec, e1buf, tmp64, qrw, qrg, qvte;
+  DBuf<int> qstat;
   DBuf<float> tmp32;
 
   // work buffers
@@ -430,6 +432,9 @@ struct st_handle {
                       int &v0next, bool exact_d, const float *y);
   hipError_t factored_product(const double *S_or_null, double *out64);
   hipError_t init_g0(int64_t R, int rk);
+  hipError_t chunk_gram(const double *X, int64_t R, int r, double *out);
+  int qr_fix(const double *Gtop, int rdi, const double *vte, const double *ee, const double *pv,
+             int nxt);
   int do_reconstruct_slice(int64_t t, float *out);
   void destroy();
 };
@@ -820,6 +825,8 @@ int st_handle::do_update(const float *y) {
     stt.ms_modes = ms_modes;
     stt.ms_total = ms_since(t0);
     stt.ms_isvd = stt.ms_total - ms_modes;
+    qr_total += stt.qr_fired;
+    stt.qr_total = qr_total;
     stats = stt;
     return ST_OK;
   }
@@ -834,8 +841,10 @@ int st_handle::do_update(const float *y) {
   if (e == hipSuccess) e = p1.ensure(rdi);
   if (e == hipSuccess) e = p2.ensure(rdi);
   if (e == hipSuccess) e = p.ensure(rdi);
+  if (e == hipSuccess) e = e1buf.ensure((size_t)Rnew);
   if (e != hipSuccess) return hipfail(e, "isvd buffers");
   IsvdArgs ia{};
+  ia.e1out = e1buf.p;  // e1 = d - V p1, kept for the second projection step
   ia.V = V[cur].p;
   ia.ldv = Rold;
   ia.r = rdi;
@@ -869,7 +878,8 @@ int st_handle::do_update(const float *y) {
   double q2 = std::max(e1sq - p2sq, 0.0);
   double q = std::sqrt(q2);
   if (!std::isfinite(q)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
-  const double *pvec = p.p;  // p of Alg. 3 on the device
+  const double *pvec = p.p;    // p of Alg. 3 on the device
+  const double *p2vec = p2.p;  // second projection: e = e1 - V p2 (the CGS2 order)
   std::vector<double> ph(hpin + 3, hpin + 3 + rdi);
   stt.q_fast = q;
   if (!exact_d && q > (1.0 - guard_rel) * eps) {
@@ -883,7 +893,7 @@ int st_handle::do_update(const float *y) {
     if (rc != ST_OK) return rc;
     const int nbd = 1024;
     e = dlt.ensure((size_t)Rnew);
-    if (e == hipSuccess) e = pref.ensure(2 * (size_t)rdi + 2);
+    if (e == hipSuccess) e = pref.ensure(3 * (size_t)rdi + 2);
     if (e == hipSuccess) e = part.ensure(2 * (size_t)nbd);
     if (e != hipSuccess) return hipfail(e, "isvd refinement buffers");
     double *vtd = pref.p, *pnew = pref.p + rdi;
@@ -894,7 +904,11 @@ int st_handle::do_update(const float *y) {
       e = launch_gemv_t_mapped(V[cur].p, Rold, map, Rnew, rdi, dlt.p, colpart.p, nbg, stream);
     if (e == hipSuccess && rdi > 0)
       e = launch_colsum(colpart.p, nbg, rdi, vtd, p.p, pnew, nullptr, nullptr, stream);
-    toc(ST_K_REFINE, 2.0 * Rnew * rdi + 4.0 * Rnew, 8.0 * Rold * rdi + 24.0 * Rnew);
+    // e1' = e1 + delta and p2' = p2 + V^T delta: the same two steps on d'
+    double *p2new = pref.p + 2 * rdi;
+    if (e == hipSuccess) e = launch_vadd(e1buf.p, dlt.p, Rnew, e1buf.p, stream);
+    if (e == hipSuccess) e = launch_vadd(p2.p, vtd, rdi, p2new, stream);
+    toc(ST_K_REFINE, 2.0 * Rnew * rdi + 5.0 * Rnew, 8.0 * Rold * rdi + 48.0 * Rnew);
     if (e == hipSuccess)
       e = launch_gather3(hpin_dev, sums.p + 16, 2, 0, vtd, rdi, 2, pnew, rdi, 2 + rdi, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -911,6 +925,7 @@ int st_handle::do_update(const float *y) {
     ph.assign(hpin + 2 + rdi, hpin + 2 + 2 * rdi);
     dvec = dex;
     pvec = pnew;
+    p2vec = p2new;
     exact_d = true;
     stt.refined_isvd = 1;
     ++stt.guard_hits;
@@ -922,11 +937,43 @@ int st_handle::do_update(const float *y) {
   const int64_t c = rd + grow;
   stt.q = q;
   stt.isvd_ignored = grow ? 0 : 1;
-  // the check of Alg. 3 on the single-pass complement: max_j |V(:,j)^T e1| / ||e1||
-  stt.orth_check = e1sq > 0.0 ? p2max / std::sqrt(e1sq) : 0.0;
-  stt.qr_fired = (grow && stt.orth_check > orth_tol) ? 1 : 0;
+  stt.orth_check = 0.0;
+  stt.qr_fired = 0;
+  (void)e1sq;
+  (void)p2max;
   if (max_rank_d > 0 && c > max_rank_d)
     return fail(ST_ECAPACITY, "streaming rank %lld exceeds the cap", (long long)c);
+  // q of S' and of v = e / q: on a growing slice the norm of e itself
+  double qv = q;
+  double *vte = nullptr, *eev = sums.p + 20;
+  if (grow) {
+    // Alg. 3's orthogonality check on the new direction, over all columns:
+    // e = e1 - V p2, V^T e and ||e||^2 in one more sweep over V
+    e = qvte.ensure((size_t)rdi + 1);
+    if (e != hipSuccess) return hipfail(e, "orthogonality check buffers");
+    vte = qvte.p;
+    IsvdArgs ic = ia;
+    ic.d = e1buf.p;
+    ic.p1 = p2vec;
+    ic.e1out = nullptr;
+    tic();
+    e = launch_isvd_pass(2, ic, nbp, stream);
+    if (e == hipSuccess)
+      e = launch_colsum(colpart.p, nbp, rdi, vte, nullptr, nullptr, q2part.p, eev, stream);
+    toc(ST_K_ORTH, 4.0 * Rnew * rdi, 8.0 * Rold * rdi + 8.0 * Rnew);
+    if (e == hipSuccess)
+      e = launch_gather3(hpin_dev, eev, 1, 0, vte, rdi, 1, nullptr, 0, 0, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "orthogonality check");
+    settle();
+    const double ee = hpin[0];
+    if (!(ee > 0.0) || !std::isfinite(ee)) return fail(ST_ENONFINITE, "non-finite ISVD residual");
+    double vmax = 0.0;
+    for (int j = 0; j < rdi; ++j) vmax = std::max(vmax, std::fabs(hpin[1 + j]));
+    qv = std::sqrt(ee);
+    stt.orth_check = vmax / qv;
+    stt.qr_fired = stt.orth_check > orth_tol ? 1 : 0;
+  }
 
   const int nxt = cur ^ 1;
   const int64_t nn = rd + 1;
@@ -949,14 +996,27 @@ int st_handle::do_update(const float *y) {
   if (e != hipSuccess) return hipfail(e, "streaming buffers");
   ud_ld[nxt] = ldn;
 
-  tic();
-  e = launch_secular_svd(secdata(rdi), S[cur].p, pvec, q, nullptr, grow, tol, (int)c, U2.p,
-                         V2.p, S[nxt].p, stream);
-  if (e == hipSuccess)
-    e = launch_build_rot_w(U2.p, V2.p, rdi, (int)c, (int)kv, grow ? 1.0 / q : 0.0, Wv.p, ldwv,
-                           Wc.p, ldwc, stream);
-  toc(ST_K_SVD, 60.0 * (double)nn * nn, 8.0 * 4.0 * nn * c);
-  if (e != hipSuccess) return hipfail(e, "small SVD");
+  if (stt.qr_fired) {
+    // [V v] = Q R through the Gram of [V v]; V^T V over the old layout (padded
+    // rows are zero)
+    tic();
+    e = qrg.ensure((size_t)rdi * rdi);
+    if (e == hipSuccess) e = chunk_gram(V[cur].p, Rold, rdi, qrg.p);
+    if (e != hipSuccess) return hipfail(e, "V^T V");
+    rc = qr_fix(qrg.p, rdi, vte, eev, pvec, nxt);
+    toc(ST_K_ORTH, 2.0 * Rold * rdi * rdi + 40.0 * (double)nn * nn * nn, 8.0 * Rold * rdi);
+    if (rc != ST_OK) return rc;
+    settle();
+  } else {
+    tic();
+    e = launch_secular_svd(secdata(rdi), S[cur].p, pvec, qv, nullptr, grow, tol, (int)c, U2.p,
+                           V2.p, S[nxt].p, stream);
+    toc(ST_K_SVD, 60.0 * (double)nn * nn, 8.0 * 4.0 * nn * c);
+    if (e != hipSuccess) return hipfail(e, "small SVD");
+  }
+  e = launch_build_rot_w(U2.p, V2.p, rdi, (int)c, (int)kv, grow ? 1.0 / qv : 0.0, Wv.p, ldwv,
+                         Wc.p, ldwc, stream);
+  if (e != hipSuccess) return hipfail(e, "rotation matrices");
   // V~ = [V v] V''  (mode-d TTM of V with the padded rows mapped)
   FiberIn vin{};
   vin.x = V[cur].p;
@@ -966,11 +1026,11 @@ int st_handle::do_update(const float *y) {
   vin.F = Rnew;
   vin.mapped = 1;
   vin.map = map;
-  vin.extra = grow ? dvec : nullptr;
+  vin.extra = grow ? e1buf.p : nullptr;
   tic();
-  // V~ = [V v] V'' with v = e / q, e = d - V p formed per row in FP64
+  // V~ = [V v] V'' with v = e / q, e = e1 - V p2 formed per row in FP64
   e = launch_rot64(vin, Wv.p, 1, ldwv, 0, (int)c, FiberOut{V[nxt].p, 1, Rnew, c}, grow ? 2 : 0,
-                   pvec, stream);
+                   p2vec, stream);
   // read V (R_old x r_d, FP64) and d, write V~ (R_new x c, FP64): 2 R_new K c flops
   toc(ST_K_ROT_V, 2.0 * Rnew * (double)kv * c + (grow ? 2.0 * Rnew * rd : 0.0),
       8.0 * ((double)Rold * rd + (grow ? Rnew : 0) + (double)Rnew * c));
@@ -1017,6 +1077,8 @@ int st_handle::do_update(const float *y) {
   stt.ms_modes = ms_modes;
   stt.ms_total = ms_since(t0);
   stt.ms_isvd = stt.ms_total - ms_modes;
+  qr_total += stt.qr_fired;
+  stt.qr_total = qr_total;
   stats = stt;
   return ST_OK;
 }
@@ -1027,10 +1089,12 @@ int st_handle::do_update(const float *y) {
 // them grew). One sweep over V0 gives t1 = V0^T d and ||d||^2; the rest of the
 // two Gram-Schmidt passes is r x r work through G0 (isvd_gram_kernel). When q
 // lands within the rounding bound of that formula of eps, the second pass is
-// redone exactly by a sweep over V0. A growing slice forms e = d - V0 (w1 + w2),
-// V0^T e and ||e||^2 in one fused sweep, appends v = e / ||e|| as a new column of
-// V0 and extends G0; in every case M~ = blockdiag(M, 1) V'' and U_d, S are updated
-// as in the literal form. On success hpin[0 .. c) holds the new singular values.
+// redone exactly by a sweep over V0. A growing slice forms e1 = d - V0 w1 and
+// then e = e1 - V0 w2 in two sweeps (each with V0^T of its result), checks the
+// orthogonality of v = e / ||e|| to V (Alg. 3, with the QR fix when it fails),
+// appends v as a new column of V0 and extends G0; in every case
+// M~ = blockdiag(M, 1) V'' and U_d, S are updated as in the literal form. On
+// success hpin[0 .. c) holds the new singular values.
 // ---------------------------------------------------------------------------
 int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
                                double eps, st_slice_stats &stt, int &grow, double &q2,
@@ -1155,8 +1219,10 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   c = rd + grow;
   stt.q = q;
   stt.isvd_ignored = grow ? 0 : 1;
-  stt.orth_check = e1sq > 0.0 ? p2max / std::sqrt(e1sq) : 0.0;
-  stt.qr_fired = (grow && stt.orth_check > orth_tol) ? 1 : 0;
+  stt.orth_check = 0.0;
+  stt.qr_fired = 0;
+  (void)e1sq;
+  (void)p2max;
   if (max_rank_d > 0 && c > max_rank_d)
     return fail(ST_ECAPACITY, "streaming rank %lld exceeds the cap", (long long)c);
 
@@ -1176,12 +1242,15 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   ud_ld[nxt] = ldn;
   tic();
   if (grow) {
-    // e = d - V0 (w1 + w2) into column r_d of V0 with V0^T e and ||e||^2 in one
-    // sweep. S' takes ||e|| itself as its q entry and v = e / ||e|| is appended,
-    // so that [V, v] stays orthonormal: the q of the G0 formula decided the
-    // growth, but it carries the rounding of a difference of terms of size
-    // ||d||^2 and is not accurate enough to normalise v (its relative error grows
-    // as (||d|| / q)^2).
+    // The new direction in the order of the two Gram-Schmidt passes, so that
+    // the rounding of the first step (about u ||d|| per row) is projected out by
+    // the second: e1 = d - V0 w1 into column r_d of V0 with V0^T e1 and ||e1||^2,
+    // the r x r part of the second pass on that exact V0^T e1 (p2, w2, p), then
+    // e = e1 - V0 w2 in place with V0^T e and ||e||^2. S' takes ||e|| itself as
+    // its q entry and v = e / ||e|| is appended, so that [V, v] stays
+    // orthonormal: the q of the G0 formula decided the growth, but it carries
+    // the rounding of a difference of terms of size ||d||^2 and is not accurate
+    // enough to normalise v (its relative error grows as (||d|| / q)^2).
     RowMap ident{};
     ident.nm = m;
     ident.identity = 1;
@@ -1192,23 +1261,70 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
     ia.R = Rnew;
     ia.map = ident;
     ia.d = dvec;
-    ia.p1 = ws;
+    ia.p1 = w1;
     ia.colpart = colpart.p;
     ia.q2part = q2part.p;
     ia.e1out = V0 + Rnew * rd;
     e = launch_isvd_pass(2, ia, nbp, stream);
     if (e == hipSuccess)
+      e = launch_colsum(colpart.p, nbp, rdi, t2, nullptr, nullptr, q2part.p, sc, stream);
+    if (e == hipSuccess)
+      e = launch_isvd_gram(M, G0, rdi, t1, dd, 1, p1.p, w1, t2, p2.p, w2, p.p, ws, sc, gv,
+                           nullptr, stream);
+    ia.d = V0 + Rnew * rd;  // e1, overwritten row by row with e
+    ia.p1 = w2;
+    if (e == hipSuccess) e = launch_isvd_pass(2, ia, nbp, stream);
+    if (e == hipSuccess)
       e = launch_colsum(colpart.p, nbp, rdi, ge, nullptr, nullptr, q2part.p, ee, stream);
     if (e == hipSuccess) e = launch_scale_rsqrt(V0 + Rnew * rd, Rnew, ee, stream);
   }
-  // the appended column: V0 and d read, one column written
-  toc(ST_K_ROT_V, grow ? 4.0 * Rnew * rd : 0.0,
-      grow ? 8.0 * ((double)Rnew * rd + 3.0 * Rnew) : 0.0);
+  // the appended column: V0 read twice, d read, the column written twice
+  toc(ST_K_ROT_V, grow ? 8.0 * Rnew * rd : 0.0,
+      grow ? 8.0 * (2.0 * Rnew * rd + 5.0 * Rnew) : 0.0);
   if (e != hipSuccess) return hipfail(e, "V0 append");
-  // S', then M~ = blockdiag(M, 1) V'' and G0 (r x r work)
+  if (grow) {
+    // Alg. 3's orthogonality check on v = e / ||e|| over all columns of
+    // V = V0 M: V^T e = M^T (V0^T e), r x r work on the sweep's V0^T e
+    e = qvte.ensure((size_t)rdi + 1);
+    if (e != hipSuccess) return hipfail(e, "orthogonality check buffers");
+    tic();
+    e = launch_small_gemv(M, rdi, ge, 1, qvte.p, nullptr, nullptr, stream);
+    toc(ST_K_ORTH, 2.0 * (double)rdi * rdi, 8.0 * (double)rdi * rdi);
+    if (e == hipSuccess)
+      e = launch_gather3(hpin_dev, ee, 1, 0, qvte.p, rdi, 1, nullptr, 0, 0, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "orthogonality check");
+    settle();
+    const double eeh = hpin[0];
+    if (!(eeh > 0.0) || !std::isfinite(eeh))
+      return fail(ST_ENONFINITE, "non-finite ISVD residual");
+    double vmax = 0.0;
+    for (int j = 0; j < rdi; ++j) vmax = std::max(vmax, std::fabs(hpin[1 + j]));
+    stt.orth_check = vmax / std::sqrt(eeh);
+    stt.qr_fired = stt.orth_check > orth_tol ? 1 : 0;
+  }
+  if (stt.qr_fired) {
+    // QR fix: V^T V = M^T G0 M (r x r products)
+    tic();
+    e = qrg.ensure(2 * (size_t)rdi * rdi);
+    if (e == hipSuccess)
+      e = launch_small_gemm(0, G0, rdi, M, rdi, qrg.p + (size_t)rdi * rdi, rdi, rdi, rdi, rdi,
+                            stream);
+    if (e == hipSuccess)
+      e = launch_small_gemm(1, M, rdi, qrg.p + (size_t)rdi * rdi, rdi, qrg.p, rdi, rdi, rdi, rdi,
+                            stream);
+    if (e != hipSuccess) return hipfail(e, "V^T V");
+    const int rc = qr_fix(qrg.p, rdi, qvte.p, ee, p.p, nxt);
+    toc(ST_K_ORTH, 4.0 * (double)rdi * rdi * rdi + 40.0 * (double)nn * nn * nn,
+        8.0 * 3.0 * rdi * rdi);
+    if (rc != ST_OK) return rc;
+    settle();
+  }
+  // S' (unless the QR fix took its SVD), then M~ = blockdiag(M, 1) V'' and G0
   tic();
-  e = launch_secular_svd(secdata(rdi), S[cur].p, p.p, q, grow ? ee : nullptr, grow, tol, (int)c,
-                         U2.p, V2.p, S[nxt].p, stream);
+  if (!stt.qr_fired)
+    e = launch_secular_svd(secdata(rdi), S[cur].p, p.p, q, grow ? ee : nullptr, grow, tol, (int)c,
+                           U2.p, V2.p, S[nxt].p, stream);
   if (e == hipSuccess) e = launch_g0_update(G0, rdi, ge, ee, grow, Gf[nxt].p, stream);
   if (e == hipSuccess) e = launch_m_update(M, rdi, V2.p, (int)c, grow, Mf[nxt].p, stream);
   toc(ST_K_SVD, 60.0 * (double)nn * nn + 2.0 * (double)c * c * rd,
@@ -1232,29 +1348,62 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
 // R products per entry; the factored ISVD test takes differences of terms of
 // size ||d||^2 through G0, so its rounding must stay at the level of the other
 // blocked sums over R rows (t1 = V0^T d, ||d||^2).
-hipError_t st_handle::init_g0(int64_t R, int rk) {
-  const size_t rr = (size_t)rk * rk;
+hipError_t st_handle::init_g0(int64_t R, int rk) { return chunk_gram(V[cur].p, R, rk, Gf[cur].p); }
+
+// out (r x r) = X^T X for a column-major R x r X (ld R): library GEMMs over row
+// chunks into separate partial Grams (in tmp64), summed in a fixed order.
+hipError_t st_handle::chunk_gram(const double *X, int64_t R, int r, double *out) {
+  const size_t rr = (size_t)r * r;
+  if (rr == 0) return hipSuccess;
   const int64_t max_parts = std::max<int64_t>(1, std::min<int64_t>(1024, (8 << 20) / (int64_t)rr));
   const int64_t ch = std::max<int64_t>(2048, (R + max_parts - 1) / max_parts);
   const int64_t nfull = R / ch, tail = R - nfull * ch;
   const int64_t nb = nfull + (tail > 0 ? 1 : 0);
+  if (nb == 0) return hipErrorInvalidValue;
   hipError_t e = tmp64.ensure((size_t)nb * rr);
   if (e != hipSuccess) return e;
   const double one = 1.0, zero = 0.0;
   rocblas_status bs = rocblas_status_success;
   if (nfull > 0)
     bs = rocblas_dgemm_strided_batched(
-        rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)rk, (rocblas_int)rk,
-        (rocblas_int)ch, &one, V[cur].p, (rocblas_int)R, (rocblas_stride)ch, V[cur].p,
-        (rocblas_int)R, (rocblas_stride)ch, &zero, tmp64.p, (rocblas_int)rk, (rocblas_stride)rr,
+        rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r, (rocblas_int)r,
+        (rocblas_int)ch, &one, X, (rocblas_int)R, (rocblas_stride)ch, X, (rocblas_int)R,
+        (rocblas_stride)ch, &zero, tmp64.p, (rocblas_int)r, (rocblas_stride)rr,
         (rocblas_int)nfull);
   if (bs == rocblas_status_success && tail > 0)
-    bs = rocblas_dgemm(rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)rk,
-                       (rocblas_int)rk, (rocblas_int)tail, &one, V[cur].p + nfull * ch,
-                       (rocblas_int)R, V[cur].p + nfull * ch, (rocblas_int)R, &zero,
-                       tmp64.p + (size_t)nfull * rr, (rocblas_int)rk);
+    bs = rocblas_dgemm(rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)r,
+                       (rocblas_int)r, (rocblas_int)tail, &one, X + nfull * ch, (rocblas_int)R,
+                       X + nfull * ch, (rocblas_int)R, &zero, tmp64.p + (size_t)nfull * rr,
+                       (rocblas_int)r);
   if (bs != rocblas_status_success) return hipErrorUnknown;
-  return launch_batch_sum(tmp64.p, (int)nb, (int64_t)rr, Gf[cur].p, stream);
+  return launch_batch_sum(tmp64.p, (int)nb, (int64_t)rr, out, stream);
+}
+
+// The QR fix of Alg. 3, taken when the orthogonality check on the new v fires:
+// [V v] = Q R and S' -> S' R^T, whose SVD is then taken densely (k_dense.hip).
+// Gtop = V^T V (r x r), vte = V^T e, ee = ||e||^2 (v = e / ||e||) and pv = p are
+// on the device. Writes U'' (U2), V'' = R^{-1} V_B (V2, so that V~ = [V v] V''
+// as without the fix) and S~ (S[nxt], descending); c = n = r + 1.
+int st_handle::qr_fix(const double *Gtop, int rdi, const double *vte, const double *ee,
+                      const double *pv, int nxt) {
+  const int n = rdi + 1;
+  const size_t nn2 = (size_t)n * n;
+  hipError_t e = qrw.ensure(3 * nn2 + n);
+  if (e == hipSuccess) e = qstat.ensure(2);
+  if (e != hipSuccess) return hipfail(e, "QR fix buffers");
+  double *G = qrw.p, *A = G + nn2, *W = A + nn2, *sig = W + nn2;
+  e = launch_qr_gram_fill(Gtop, rdi, vte, ee, G, stream);
+  if (e == hipSuccess) e = launch_chol_upper(G, n, qstat.p, stream);
+  if (e == hipSuccess) e = launch_arrow_rt(S[cur].p, pv, ee, G, rdi, A, stream);
+  if (e == hipSuccess) e = launch_jacobi_svd(A, n, W, 60, qstat.p, stream);
+  if (e == hipSuccess) e = launch_jacobi_finish(A, W, G, n, U2.p, V2.p, S[nxt].p, sig, stream);
+  int st[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(st, qstat.p, sizeof(st), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "QR fix");
+  if (st[0] == 1) return fail(ST_ESOLVER, "QR fix: the Gram of [V v] is not positive definite");
+  if (st[0] == 2) return fail(ST_ESOLVER, "QR fix: Jacobi SVD did not converge");
+  return ST_OK;
 }
 
 // V0 M diag(S) (S not null: the core C_(d)^T) or V0 M (V) into out64 (R x r_d).
@@ -1367,6 +1516,10 @@ void st_handle::destroy() {
   wvec.release();
   e1buf.release();
   tmp64.release();
+  qrw.release();
+  qrg.release();
+  qvte.release();
+  qstat.release();
   tmp32.release();
   part.release();
   sums.release();
@@ -1456,7 +1609,7 @@ int st_create(const st_config *cfg, st_handle **out) {
   h->tau = cfg->tau;
   h->prec = cfg->precision == ST_BF16X3 ? Prec::BF16X3
                                         : (cfg->precision == ST_FP64 ? Prec::FP64 : Prec::FP32);
-  h->orth_tol = cfg->orth_tol > 0.0 ? cfg->orth_tol : 1e-5;
+  h->orth_tol = cfg->orth_tol > 0.0 ? cfg->orth_tol : 1e-12;
   h->guard_rel = cfg->guard_rel > 0.0
                      ? cfg->guard_rel
                      : (h->prec == Prec::BF16X3 ? 5e-2 : (h->prec == Prec::FP32 ? 1e-2 : 0.0));

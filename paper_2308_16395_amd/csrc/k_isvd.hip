@@ -1138,6 +1138,19 @@ hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, 
   return hipGetLastError();
 }
 
+// out = a + b (n entries; out may alias a or b)
+__global__ void vadd_kernel(const double *a, const double *b, int64_t n, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+hipError_t launch_vadd(const double *a, const double *b, int64_t n, double *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vadd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n,
+                     out);
+  return hipGetLastError();
+}
+
 // x /= sqrt(ss[0]) (ss on the device: a sum of squares formed by an earlier launch)
 __global__ void scale_rsqrt_kernel(double *x, int64_t n, const double *ss) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

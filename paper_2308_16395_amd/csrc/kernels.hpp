@@ -94,6 +94,21 @@ hipError_t launch_isvd_gram(const double *M, const double *G0, int r, const doub
 hipError_t launch_g0_update(const double *G0, int r, const double *g, const double *ee, int grow,
                             double *Gn, hipStream_t s);
 hipError_t launch_scale_rsqrt(double *x, int64_t n, const double *ss, hipStream_t s);
+hipError_t launch_vadd(const double *a, const double *b, int64_t n, double *out, hipStream_t s);
+// QR fix of Alg. 3 (k_dense.hip): Gram of [V v], its Cholesky factor R,
+// B = S' R^T, one-sided Jacobi SVD of B and the finished U'', V'' = R^{-1} V_B,
+// S (descending). status[0]: 0 ok, 1 not positive definite, 2 no convergence;
+// status[1]: sweeps taken.
+hipError_t launch_qr_gram_fill(const double *Gtop, int r, const double *vte, const double *ee,
+                               double *G, hipStream_t s);
+hipError_t launch_chol_upper(double *G, int n, int *status, hipStream_t s);
+hipError_t launch_arrow_rt(const double *S, const double *p, const double *ee, const double *R,
+                           int r, double *B, hipStream_t s);
+hipError_t launch_jacobi_svd(double *A, int n, double *W, int max_sweeps, int *status,
+                             hipStream_t s);
+hipError_t launch_jacobi_finish(const double *A, const double *W, const double *R, int n,
+                                double *U2, double *V2, double *Snew, double *sig,
+                                hipStream_t s);
 // out[i] = sum over b < nb of part[b * n + i], in a fixed order
 hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, hipStream_t s);
 // delta = a - b (n rows) and per-block pairs (sum b * delta, sum delta^2) in

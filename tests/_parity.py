@@ -25,7 +25,8 @@ def margins(rec):
 
 
 def run_parity(stream, n_slices, n_init, tau, precision="fp32", err_tol=1e-5,
-               probe_every=1, marginal=1e-3, guard_rel=0.0, core_update="literal"):
+               probe_every=1, marginal=1e-3, guard_rel=0.0, core_update="literal",
+               orth_tol=0.0, eps_m=1e-12):
     """Stream the same float32 slices through the GPU path and the oracle.
 
     Returns a dict with the per-slice rank sequences, the worst error of the GPU
@@ -38,9 +39,9 @@ def run_parity(stream, n_slices, n_init, tau, precision="fp32", err_tol=1e-5,
 
     flat, shaped = slices32(stream, n_slices)
     x0 = np.concatenate(flat[:n_init])
-    orc = Oracle(np.stack(shaped[:n_init], axis=-1), tau, core_update=core_update)
+    orc = Oracle(np.stack(shaped[:n_init], axis=-1), tau, core_update=core_update, eps_m=eps_m)
     gpu = pkg.StreamingTucker(stream.dims, tau, precision=precision, guard_rel=guard_rel,
-                              core_update=core_update)
+                              core_update=core_update, orth_tol=orth_tol)
     gpu.init(torch.from_numpy(x0).cuda(), n_init)
     out = dict(gpu_ranks=[gpu.ranks], orc_ranks=[orc.ranks], worst_err=0.0, diverged_at=None,
                margin_at_divergence=None, stats=[])

@@ -62,15 +62,19 @@ def test_blobs_tau1e4_d5_medium_fp64_products():
     ign_gpu = sum(st["isvd_ignored"] for st in res["stats"])
     ign_orc = sum(h["ignored"] for h in orc.history)
     assert ign_gpu == ign_orc
-    # V from the Gram-based initial SVD (Alg. 1) is orthonormal only to about
-    # u * kappa^2 (about 1e-8 in the oracle on this stream), so the single-pass
-    # measure max |V^T e1| / ||e1|| sits far above rounding on both sides and
-    # grows as ||d|| / q grows (the oracle's reaches 6.8e-6 here). Its size is
-    # set by how each side's rounding of V lines up with the slices, so the
-    # GPU's must be of the oracle's order over the stream.
-    gpu_orth = [st["orth_check"] for st in res["stats"]]
-    orc_orth = [h["orth_single_pass"] for h in orc.history]
-    assert max(gpu_orth) <= 10.0 * max(orc_orth), (max(gpu_orth), max(orc_orth))
+    # Alg. 3's orthogonality check on the new direction, over all columns of V.
+    # After two Gram-Schmidt passes V^T v is about ||V^T V - I||^2 ||d|| / q: V
+    # from the Gram-based initial SVD (Alg. 1) is orthonormal to about 1e-8, so
+    # the check sits near eps_m = 1e-12 on both sides (the oracle's reaches
+    # 2.8e-13 here) and whether it crosses eps_m on a given slice depends on how
+    # each side's rounding of V lines up. Checked: the GPU's values are of the
+    # oracle's order, and the GPU takes the QR fix exactly where its own check
+    # exceeds eps_m.
+    grow_gpu = [st["orth_check"] for st in res["stats"] if not st["isvd_ignored"]]
+    grow_orc = [h["orth_check"] for h in orc.history if not h["ignored"]]
+    assert len(grow_gpu) == len(grow_orc) > 0
+    assert all(bool(st["qr_fired"]) == (st["orth_check"] > 1e-12) for st in res["stats"])
+    assert max(grow_gpu) <= 10.0 * max(grow_orc), (sorted(grow_gpu)[-5:], max(grow_orc))
 
 
 FAST = [("fp32", "literal", 1e-5), ("fp32", "factored", 1e-5), ("bf16x3", "literal", 1e-4),
