@@ -27,7 +27,9 @@
  *    Python framework); its stream handles are not valid here and its queued
  *    work is not ordered with this library's: the caller must finish the work
  *    that produces an input (or last used an output buffer) before the call.
- *  - st_update is transactional: on any error the decomposition is unchanged.
+ *  - st_update is transactional: on any error the decomposition is unchanged,
+ *    and an update whose new singular values fail validation at the next
+ *    synchronisation is rolled back before anything else changes (st_update).
  */
 #ifndef STUCKER_H
 #define STUCKER_H
@@ -166,9 +168,11 @@ typedef struct st_slice_stats {
 
 typedef struct st_handle st_handle;
 
-/* Create an empty handle and allocate its fixed device state (factors U_k at
- * full capacity n_k x n_k). Ownership: the handle owns all device memory until
- * st_destroy. Errors: ST_EINVAL (bad dims, tau <= 0, nmodes out of range),
+/* Create an empty handle for a d-way stream whose last mode is the streaming
+ * (time) mode (the setting of Sec. 3: slices of size n_1 x ... x n_{d-1}
+ * arrive one at a time), and allocate its fixed device state (factors U_k at
+ * full capacity n_k x n_k, since Alg. 4 only appends columns to them).
+ * Ownership: the handle owns all device memory until st_destroy. Errors: ST_EINVAL (bad dims, tau <= 0, nmodes out of range),
  * ST_ENOMEM, ST_EHIP. */
 int st_create(const st_config *cfg, st_handle **out);
 
@@ -191,15 +195,23 @@ int st_init(st_handle *h, const float *x0, int64_t n_init);
  * queues behind it without an idle gap. Every later call on the handle orders
  * after it. y is read only before the first internal synchronisation, so it
  * may be reused when the call returns. The new singular values
- * are checked when they are next read (the next st_update or st_sv): a
- * non-positive value is reported there as ST_ESOLVER. */
+ * are validated at the next synchronisation (the next st_update, or any call
+ * that reads the decomposition): should one not be positive, that update is
+ * rolled back (ranks, counters and the ping-pong halves of the device state
+ * return to their values before it, nothing having been overwritten) and the
+ * call that found it returns ST_ESOLVER without doing its own work. */
 int st_update(st_handle *h, const float *y);
 
-/* Current ranks r_1..r_d (ranks[0..d-1]) and the number of slices n_d seen. */
+/* Current ranks r_1..r_d (ranks[0..d-1]) of the Tucker decomposition
+ * X ~ C x_1 U_1 ... x_d U_d (Sec. 2.2) and the number of slices n_d seen (the
+ * row count of U_d, Alg. 5). Host counters only: no synchronisation, so it
+ * reports the last update even while its singular values are unvalidated. */
 int st_ranks(const st_handle *h, int64_t *ranks, int64_t *n_d);
 
-/* Dense core C (r_1 x ... x r_d, column-major, float32) into out (host or
- * device pointer per `where`). out == NULL only sets *need (elements).
+/* Dense core C (r_1 x ... x r_d, column-major, float32) of the decomposition
+ * (Sec. 2.2; the core kept by Alg. 5, or V x_d S in the factored form of
+ * Sec. 3.2) into out (host or device pointer per `where`). out == NULL only
+ * sets *need (elements).
  * Errors: ST_ESMALL (cap < need; *need is set), ST_ESTATE, ST_EINVAL. */
 int st_core(const st_handle *h, float *out, int64_t cap, int64_t *need, int where);
 
@@ -210,13 +222,17 @@ int st_core(const st_handle *h, float *out, int64_t cap, int64_t *need, int wher
  * Errors: ST_ESMALL, ST_ESTATE, ST_EINVAL. */
 int st_aux_v(const st_handle *h, double *out, int64_t cap, int64_t *need, int where);
 
-/* Dense factor U_mode (mode 0..d-1; mode d-1 is the streaming factor of size
- * n_d x r_d), column-major float64, into out (host or device). out == NULL only
+/* Dense factor U_mode (Sec. 2.2; mode 0..d-1, orthonormal columns; mode d-1 is
+ * the streaming factor of size n_d x r_d that Alg. 3 extends by one row per
+ * slice), column-major float64, into out (host or device). out == NULL only
  * sets *rows and *cols. Errors: ST_EINVAL, ST_ESMALL, ST_ESTATE. */
 int st_factor(const st_handle *h, int mode, double *out, int64_t cap,
               int64_t *rows, int64_t *cols, int where);
 
-/* The diagonal S (r_d values, descending) of C = V x_d S into host memory. */
+/* The diagonal S (r_d values, descending, positive) of the core factorization
+ * C = V x_d S (Sec. 3.2, Assumption 1(c)), i.e. the singular values the ISVD of
+ * Alg. 3 maintains, into host memory. Errors: ST_ESMALL (cap < count; *count is
+ * set), ST_ESOLVER (a pending update was rolled back, see st_update). */
 int st_sv(const st_handle *h, double *s, int64_t cap, int64_t *count);
 
 /* Certified bound on ||X - X^||_F / ||X||_F: sqrt(sum of discarded energy) over
@@ -225,12 +241,15 @@ int st_sv(const st_handle *h, double *s, int64_t cap, int64_t *count);
  * ignores e (Prop. 1, App. D). norm_x = ||X||_F of all data seen. */
 int st_recon_error(const st_handle *h, double *rel_bound, double *norm_x);
 
-/* Diagnostics of the last st_update (or st_init). */
+/* Diagnostics of the last st_update (or st_init): the per-slice tolerance eps
+ * and residual norms of Alg. 5 and Alg. 4, q and the orthogonality check of
+ * Alg. 3, and the refinements of the reduced-precision forms. Host copy only. */
 int st_stats(const st_handle *h, st_slice_stats *out);
 
-/* Slice t (0-based, t < n_d) of the reconstruction C x_1 U_1 ... x_d U_d,
- * written as float32 column-major n_1 x ... x n_{d-1} to the device pointer
- * out. Errors: ST_EINVAL (t out of range), ST_ESTATE. */
+/* Slice t (0-based, t < n_d) of the reconstruction C x_1 U_1 ... x_d U_d
+ * (the Tucker model of Sec. 2.2: row t of U_d contracted with the core, then
+ * modes 1..d-1), written as float32 column-major n_1 x ... x n_{d-1} to the
+ * device pointer out. Errors: ST_EINVAL (t out of range), ST_ESTATE. */
 int st_reconstruct_slice(const st_handle *h, int64_t t, float *out);
 
 /* Stateless mode-k TTM (Sec. 2.1): out = X x_mode A, for X a dense

@@ -265,15 +265,66 @@ struct st_handle {
     return e;
   }
   // After a stream synchronisation: take the last update's singular values.
+  // The host state an update changes at its commit. Device state needs no copy:
+  // an update writes its new V / C / M / G0 / U_d / S into the other half of
+  // each ping-pong pair and its new factor or V0 columns past the committed
+  // ranks, and the next update overwrites neither before it has validated the
+  // pending singular values (its first synchronisation).
+  struct Committed {
+    int64_t r[ST_MAX_MODES];
+    int64_t rd, nd;
+    int cur, v0cur;
+    double xnorm2, disc;
+    st_slice_stats stats;
+    int64_t qr_total;
+  } prev{};
+  void snapshot() {
+    std::copy(r, r + ST_MAX_MODES, prev.r);
+    prev.rd = rd;
+    prev.nd = nd;
+    prev.cur = cur;
+    prev.v0cur = v0cur;
+    prev.xnorm2 = xnorm2;
+    prev.disc = disc;
+    prev.stats = stats;
+    prev.qr_total = qr_total;
+  }
+  void rollback() {
+    std::copy(prev.r, prev.r + ST_MAX_MODES, r);
+    rd = prev.rd;
+    nd = prev.nd;
+    cur = prev.cur;
+    v0cur = prev.v0cur;
+    xnorm2 = prev.xnorm2;
+    disc = prev.disc;
+    stats = prev.stats;
+    qr_total = prev.qr_total;
+  }
+  // Validates the singular values the last update published without a
+  // synchronisation (call after one). If one is not positive, that update is
+  // undone and the error is reported by this call: the state is the one before
+  // it, as if it had failed.
   int finish_pending() {
     if (!s_pending) return ST_OK;
     const int64_t c = s_pending;
     s_pending = 0;
     for (int64_t i = 0; i < c; ++i)
-      if (!std::isfinite(hS[i]) || hS[i] <= 0.0)
-        return fail(ST_ESOLVER, "small SVD produced a non-positive singular value");
+      if (!std::isfinite(hS[i]) || hS[i] <= 0.0) {
+        rollback();
+        return fail(ST_ESOLVER,
+                    "the last update was rolled back: its small SVD produced a non-positive "
+                    "singular value");
+      }
     S_host.assign(hS, hS + c);
     return ST_OK;
+  }
+  // Synchronises and validates a pending publication (readers of the state).
+  int take_pending() {
+    if (!s_pending) return ST_OK;
+    const hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "pending update");
+    settle();
+    return finish_pending();
   }
 
   // Pinned scratch for the scalars and short vectors the host reads back. It is
@@ -810,6 +861,7 @@ int st_handle::do_update(const float *y) {
     rc = stream_factored(map, dvec, Rold, Rnew, eps, stt, growf, q2f, cf, v0next, exact_d, y);
     if (rc != ST_OK) return rc;
     // ---- commit (the singular values follow through hS) ----
+    snapshot();
     s_pending = cf;
     for (int k = 0; k < m; ++k) r[k] = rn[k];
     rd = cf;
@@ -1063,6 +1115,7 @@ int st_handle::do_update(const float *y) {
   if (e != hipSuccess) return hipfail(e, "streaming update");
 
   // ---- commit ----
+  snapshot();
   s_pending = c;
   for (int k = 0; k < m; ++k) r[k] = rn[k];
   rd = c;
@@ -1682,6 +1735,8 @@ int st_core(const st_handle *hc, float *out, int64_t cap, int64_t *need, int whe
   st_handle *h = const_cast<st_handle *>(hc);
   if (!h) return ST_EINVAL;
   if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
+  (void)hipSetDevice(h->device);
+  if (const int rc = h->take_pending(); rc != ST_OK) return rc;
   const int64_t cnt = h->rprod(h->r, h->m) * h->rd;
   if (need) *need = cnt;
   if (!out) return ST_OK;
@@ -1710,6 +1765,8 @@ int st_aux_v(const st_handle *hc, double *out, int64_t cap, int64_t *need, int w
   st_handle *h = const_cast<st_handle *>(hc);
   if (!h) return ST_EINVAL;
   if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
+  (void)hipSetDevice(h->device);
+  if (const int rc = h->take_pending(); rc != ST_OK) return rc;
   const int64_t cnt = h->rprod(h->r, h->m) * h->rd;
   if (need) *need = cnt;
   if (!out) return ST_OK;
@@ -1736,6 +1793,8 @@ int st_factor(const st_handle *hc, int mode, double *out, int64_t cap, int64_t *
   st_handle *h = const_cast<st_handle *>(hc);
   if (!h) return ST_EINVAL;
   if (!h->inited) return h->fail(ST_ESTATE, "not initialised");
+  (void)hipSetDevice(h->device);
+  if (const int rc = h->take_pending(); rc != ST_OK) return rc;
   if (mode < 0 || mode > h->m) return h->fail(ST_EINVAL, "mode out of range");
   const int64_t nr = (mode < h->m) ? h->n[mode] : h->nd;
   const int64_t nc = (mode < h->m) ? h->r[mode] : h->rd;
@@ -1761,13 +1820,8 @@ int st_factor(const st_handle *hc, int mode, double *out, int64_t cap, int64_t *
 int st_sv(const st_handle *hc, double *s, int64_t cap, int64_t *count) {
   if (!hc) return ST_EINVAL;
   st_handle *h = const_cast<st_handle *>(hc);  // takes a pending publication
-  if (h->s_pending) {
-    const hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return h->hipfail(e, "singular values");
-    h->settle();
-    const int rc = h->finish_pending();
-    if (rc != ST_OK) return rc;
-  }
+  const int rc = h->take_pending();
+  if (rc != ST_OK) return rc;
   if (count) *count = (int64_t)h->S_host.size();
   if (!s) return ST_OK;
   if (cap < (int64_t)h->S_host.size()) return ST_ESMALL;
@@ -1775,9 +1829,12 @@ int st_sv(const st_handle *hc, double *s, int64_t cap, int64_t *count) {
   return ST_OK;
 }
 
-int st_recon_error(const st_handle *h, double *rel_bound, double *norm_x) {
+int st_recon_error(const st_handle *hc, double *rel_bound, double *norm_x) {
+  st_handle *h = const_cast<st_handle *>(hc);
   if (!h) return ST_EINVAL;
   if (!h->inited) return ST_ESTATE;
+  (void)hipSetDevice(h->device);
+  if (const int rc = h->take_pending(); rc != ST_OK) return rc;
   if (rel_bound) *rel_bound = h->xnorm2 > 0 ? std::sqrt(h->disc / h->xnorm2) : 0.0;
   if (norm_x) *norm_x = std::sqrt(h->xnorm2);
   return ST_OK;
@@ -1793,6 +1850,7 @@ int st_reconstruct_slice(const st_handle *hc, int64_t t, float *out) {
   st_handle *h = const_cast<st_handle *>(hc);
   if (!h) return ST_EINVAL;
   (void)hipSetDevice(h->device);
+  if (const int rc = h->take_pending(); rc != ST_OK) return rc;
   return h->do_reconstruct_slice(t, out);
 }
 
