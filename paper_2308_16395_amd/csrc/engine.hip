@@ -887,7 +887,7 @@ int st_handle::do_update(const float *y) {
   // through the row map), then one sweep forming e1 = d - V p1 with ||e1||^2 and
   // p2 = V^T e1; p = p1 + p2 and q^2 = ||e1||^2 - ||p2||^2
   const int nbg = gemv_t_blocks(Rnew);
-  const int nbp = isvd_blocks(Rnew);
+  const int nbp = isvd_blocks(Rnew, rdi);
   e = colpart.ensure((size_t)(rdi + 1) * std::max(nbg, nbp));
   if (e == hipSuccess) e = q2part.ensure(nbp);
   if (e == hipSuccess) e = p1.ensure(rdi);
@@ -1175,7 +1175,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
   const double *M = Mf[cur].p;
   const double *G0 = Gf[cur].p;
   const int nbg = gemv_t_blocks(Rnew);
-  const int nbp = isvd_blocks(Rnew);
+  const int nbp = isvd_blocks(Rnew, rdi);
   e = colpart.ensure((size_t)(rdi + 1) * std::max(nbg, nbp));
   if (e == hipSuccess) e = q2part.ensure(nbp);
   if (e == hipSuccess) e = p1.ensure(rdi);

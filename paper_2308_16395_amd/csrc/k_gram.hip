@@ -437,6 +437,12 @@ hipError_t launch_fiber_project(const FiberIn &in, const FiberW &w, int m0, int 
   if (prec == Prec::BF16X3 && (w.w_hi == nullptr || w.w_lo == nullptr))
     return hipErrorInvalidValue;
   if (prec == Prec::FP32 && w.w == nullptr) return hipErrorInvalidValue;
+  // Split-bf16 products pay off only where the contraction is MFMA-bound on
+  // FP32 data. Over an FP64 partial core (modes 2..d-1) the kernels are bound
+  // by the 8-byte input and the per-element splits cost VALU time for nothing
+  // (measured: 76 vs 30 us per mode at 128^3 x 16); they take FP32 products,
+  // whose rounding (2^-24 relative per product) is that of bf16x3.
+  if (prec == Prec::BF16X3 && in.x64 && w.w != nullptr) prec = Prec::FP32;
   if (ttm_contig_eligible(in, m0, mcount, out, prec, resid_partials != nullptr))
     return launch_ttm_contig(in, w, mcount, out, resid_partials, prec, s, nparts);
   if (!in.x64 && !out.o64)

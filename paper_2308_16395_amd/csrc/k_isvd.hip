@@ -150,6 +150,80 @@ __global__ __launch_bounds__(256) void isvd_pass_kernel(IsvdArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Second Gram-Schmidt pass with V held in registers (r <= 4 CPL): a block of
+// four waves walks 64-row tiles; lane l of wave w loads row (tile * 64 + l) of
+// the columns j = w + 4 c (coalesced 512-byte column segments, one load per
+// column, all in flight together), forms its share of the row dot V(row,:) p1,
+// the four shares meet in LDS (one barrier per tile, double-buffered), and every
+// lane then has e1(row) = d(row) - V(row,:) p1 and adds V(row, j) e1(row) to its
+// column accumulators. V goes through registers once, with no LDS staging of
+// tiles; the column sums are reduced across lanes once per block at the end.
+// Same outputs as isvd_pass_kernel<2, TR>.
+// ---------------------------------------------------------------------------
+template <int CPL>
+__global__ __launch_bounds__(256) void isvd_pass2_reg_kernel(IsvdArgs a) {
+  __shared__ double dots[2][4][64];
+  __shared__ double p1s[4 * CPL];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = a.r;
+  for (int j = threadIdx.x; j < 4 * CPL; j += blockDim.x) p1s[j] = j < r ? a.p1[j] : 0.0;
+  __syncthreads();
+  double cacc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) cacc[c] = 0.0;
+  double q2 = 0.0;
+  const int64_t ntiles = (a.R + 63) / 64;
+  int buf = 0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row = tile * 64 + lane;
+    const bool valid = row < a.R;
+    const int64_t src = valid ? map_new_to_old(a.map, row) : -1;
+    // Every load is unconditional (a select right after a load would make the
+    // wave wait for it before issuing the next): a padded row reads row 0 and
+    // columns past r re-read column r - 1; both are masked where consumed (the
+    // row by zeroing its dot and e1, the columns by p1 = 0 and by never being
+    // stored).
+    double v[CPL];
+    const double *pc = a.V + (src >= 0 ? src : 0) + a.ldv * (int64_t)(wid < r ? wid : r - 1);
+    const int64_t step = 4 * a.ldv;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      v[c] = *pc;
+      if (wid + 4 * (c + 1) < r) pc += step;
+    }
+    const double dv = a.d[valid ? row : 0];
+    double dot = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) dot += v[c] * p1s[wid + 4 * c];
+    dots[buf][wid][lane] = src >= 0 ? dot : 0.0;
+    __syncthreads();
+    const double e1 =
+        valid ? dv - (((dots[buf][0][lane] + dots[buf][1][lane]) + dots[buf][2][lane]) +
+                      dots[buf][3][lane])
+              : 0.0;
+    const double e1m = src >= 0 ? e1 : 0.0;
+    if (wid == 0) {
+      if (valid && a.e1out) a.e1out[row] = e1;
+      q2 += e1 * e1;
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) cacc[c] += v[c] * e1m;
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int j = wid + 4 * c;
+    const double t = wave_sum(cacc[c]);
+    if (lane == 0 && j < r) a.colpart[(size_t)j * gridDim.x + blockIdx.x] = t;
+  }
+  if (wid == 0) {
+    const double t = wave_sum(q2);
+    if (lane == 0) a.q2part[blockIdx.x] = t;
+  }
+}
+
 // dst[oa + i] = a[i] (i < na), dst[ob + i] = b[i] (i < nb), dst[oc + i] = c[i]
 // (i < nc): one launch that publishes small results, typically into pinned
 // host memory mapped for the device (no copy engine or blit per array).
@@ -191,9 +265,14 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double *part, int nb,
   }
 }
 
-int isvd_blocks(int64_t R) {
+// Grid of the second pass: the register-resident kernel (r <= 192) keeps its
+// column sums per block until the end, so larger r takes fewer, longer-lived
+// blocks (measured at R = 948480: r = 166 runs 241 us with 512 blocks against
+// 258 us with 2048; r = 40 prefers 2048).
+int isvd_blocks(int64_t R, int r) {
   const int64_t t = (R + 63) / 64;
-  return (int)(t < 2048 ? (t > 0 ? t : 1) : 2048);
+  const int64_t cap = (r <= 32 || r > 192) ? 2048 : (r <= 64 ? 1024 : 512);
+  return (int)(t < cap ? (t > 0 ? t : 1) : cap);
 }
 
 // rowred holds 256 doubles for either tile height
@@ -216,6 +295,14 @@ static hipError_t launch_isvd_tr(const IsvdArgs &a, int nblocks, hipStream_t s) 
 
 hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s) {
   if (a.r > 8 * 256 || pass < 1 || pass > 2) return hipErrorInvalidValue;
+  if (pass == 2 && a.r >= 1 && a.r <= 4 * 48) {
+    const dim3 g((unsigned)nblocks), b(256);
+    if (a.r <= 4 * 8) hipLaunchKernelGGL(isvd_pass2_reg_kernel<8>, g, b, 0, s, a);
+    else if (a.r <= 4 * 16) hipLaunchKernelGGL(isvd_pass2_reg_kernel<16>, g, b, 0, s, a);
+    else if (a.r <= 4 * 32) hipLaunchKernelGGL(isvd_pass2_reg_kernel<32>, g, b, 0, s, a);
+    else hipLaunchKernelGGL(isvd_pass2_reg_kernel<48>, g, b, 0, s, a);
+    return hipGetLastError();
+  }
   // 64-row tiles while two blocks fit a CU's LDS, else 32-row tiles (one block
   // per CU leaves the tile load and the two compute phases unoverlapped)
   const bool tall = 2 * isvd_lds(a.r, 64) <= kIsvdMaxLds;

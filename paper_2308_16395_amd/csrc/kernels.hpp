@@ -19,7 +19,7 @@ struct IsvdArgs {
   double *e1out;       // [R] optional copy of e1 (pass 2)
 };
 
-int isvd_blocks(int64_t R);
+int isvd_blocks(int64_t R, int r);
 hipError_t launch_gather3(double *dst, const double *a, int na, int oa, const double *b, int nb,
                           int ob, const double *c, int nc, int oc, hipStream_t s);
 hipError_t launch_isvd_pass(int pass, IsvdArgs a, int nblocks, hipStream_t s);
