@@ -40,9 +40,13 @@ WORKLOAD = dict(space=(128, 128, 128), n_vars=16, n_blobs=32, n_slices=400, n_in
 
 # HBM bytes per launch of the dominant kernel of a run, from the two counter
 # passes (FETCH_SIZE, WRITE_SIZE; calibrated on a 1 GiB copy) recorded under
-# profiles/. Keyed by (precision, core update, kernel group); only reported
-# while the kernel and the timed window are those the counters were taken on.
-MEASURED_TRAFFIC = {}
+# profiles/. Keyed by (precision, core update, kernel group, timed steps); only
+# reported for the kernel and timed window the counters were taken on.
+MEASURED_TRAFFIC = {
+    # V rotation, default timed window (slices 210..399): FETCH_SIZE 492782.1
+    # KiB x 2.000 + WRITE_SIZE 974950.2 KiB x 1.000 per launch
+    ("fp32", "literal", "rot_v", 190): 2.0076e9,
+}
 
 # Differentiation workload: a 96^3 x 8 variables x 16-slice window, ranks
 # (24, 24, 24, 6, 8).
@@ -53,7 +57,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def roofline(prof, precision, core="literal"):
+def roofline(prof, precision, core="literal", steps=None):
     """Roofline entry of the group with the most device time."""
     group = max(prof, key=lambda g: prof[g]["ms"])
     p = prof[group]
@@ -75,7 +79,7 @@ def roofline(prof, precision, core="literal"):
     entry.update(kernel=group, launches=p["launches"], avg_ms=round(p["ms"] / p["launches"], 5),
                  flops_per_launch=p["flops"] / p["launches"],
                  bytes_per_launch=p["bytes"] / p["launches"],
-                 traffic=MEASURED_TRAFFIC.get((precision, core, group)))
+                 traffic=MEASURED_TRAFFIC.get((precision, core, group, steps)))
     return group, entry
 
 
@@ -537,7 +541,7 @@ def main():
         return info, prof, whole
 
     head, prof, whole = run(args.precision, args.core_update)
-    group, roof = roofline(prof, args.precision, args.core_update)
+    group, roof = roofline(prof, args.precision, args.core_update, args.steps)
     result = {
         "metric": METRIC,
         "value": head["value"],
@@ -587,7 +591,7 @@ def main():
 
                 def variant(prec=prec, core=core):
                     info, vprof, vwhole = run(prec, core)
-                    info["roofline"] = roofline(vprof, prec, core)[1]
+                    info["roofline"] = roofline(vprof, prec, core, args.steps)[1]
                     info["ttm_roofline"] = ttm_roofline(vprof, prec)
                     info["gram_roofline"] = gram_roofline(vwhole, prec)
                     info["ttm_ms"] = round(vprof["ttm1"]["ms"] + vprof["ttm"]["ms"], 3)
