@@ -16,6 +16,7 @@ from .tucker import (  # noqa: F401
     tsvd_gram,
     sthosvd,
     isvd,
+    block_isvd,
     non_streaming_update,
     StreamingTucker,
     vec,

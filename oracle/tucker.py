@@ -206,6 +206,62 @@ def isvd(u, s, v, b, eps, eps_m=1e-12, cgs2=True):
     return u_new, s_new, v_new, info
 
 
+def block_isvd(u, s, v, bmat, eps, eps_m=1e-12):
+    """Alg. 3 for a block of b new rows at once (the columns of ``bmat``, R x b).
+
+    The paper processes one slice per update and names several slices at once
+    as future work (Sec. 6); this is the block form the single-row steps
+    generalise to. Each new row is split against the span of V by the same two
+    Gram-Schmidt passes; the residual block E (R x b) takes the place of e, and
+    which of its directions to keep is the TruncatedSVD of Alg. 1 applied to E:
+    the eigenpairs (lambda_i, w_i) of the Gram E^T E, and the smallest l whose
+    tail lambda_{l+1} + ... + lambda_b is at most eps^2 (for b = 1 this keeps e
+    exactly when ||e|| > eps). The kept directions Q = E W_l Lambda_l^{-1/2}
+    extend V, and the middle matrix becomes
+
+        S' = [[diag(S), 0], [P^T, W_l Lambda_l^{1/2}]]     ((r + b) x (r + l)),
+
+    since row j of the block is p_j^T V^T + sum_i sqrt(lambda_i) W[j, i] Q_i^T
+    up to the discarded tail. The orthogonality check covers V^T Q and
+    Q^T Q - I; when it exceeds eps_m, [V Q] = Q' R' and S' -> S' R'^T as in
+    Alg. 3. Returns ``(U~, S~, V~, info)`` with U~ = blockdiag(U, I_b) U''.
+    """
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    bmat = np.asarray(bmat, dtype=np.float64)
+    r, b = s.shape[0], bmat.shape[1]
+    p = v.T @ bmat
+    e = bmat - v @ p
+    p2 = v.T @ e
+    e = e - v @ p2
+    p = p + p2
+    ell, w, sq, tail, lam = tsvd_gram(e.T, eps)
+    q = e @ w / sq[None, :] if ell > 0 else np.zeros((v.shape[0], 0))
+    k_mat = np.zeros((r + b, r + ell))
+    k_mat[:r, :r] = np.diag(s)
+    k_mat[r:, :r] = p.T
+    k_mat[r:, r:] = w * sq[None, :]
+    v_prime = np.hstack([v, q])
+    orth = 0.0
+    if ell > 0:
+        orth = float(np.max(np.abs(q.T @ q - np.eye(ell))))
+        if r > 0:
+            orth = max(orth, float(np.max(np.abs(v.T @ q))))
+    fired = ell > 0 and orth > eps_m
+    if fired:
+        qm, rm = np.linalg.qr(v_prime)
+        v_prime = qm
+        k_mat = k_mat @ rm.T
+    u2, s_new, v2t = np.linalg.svd(k_mat, full_matrices=False)
+    n = u.shape[0]
+    u_new = np.vstack([u @ u2[:r, :], u2[r:, :]])
+    v_new = v_prime @ v2t.T
+    assert u_new.shape == (n + b, r + ell)
+    info = dict(p=p, ell=ell, lam=lam, tail=tail, qr=fired, orth_check=orth, u2=u2)
+    return u_new, s_new, v_new, info
+
+
 # ----------------------------------------------------------------------------
 # Alg. 4: non-streaming mode update
 # ----------------------------------------------------------------------------
@@ -366,5 +422,62 @@ class StreamingTucker:
         rec.update(q=info["q"], ignored=bool(info["ignored"]), qr=info["qr"],
                    orth_single_pass=info["orth_single_pass"], orth_check=info["orth_check"],
                    delta2=delta2, ranks=self.ranks)
+        self.history.append(rec)
+        return rec
+
+    def update_block(self, yb):
+        """Alg. 5 for b slices at once: ``yb`` has the slice shape plus a last
+        mode of size b (the slices in stream order).
+
+        The per-update tolerance is that of the block, eps = tau ||Y_B|| / sqrt(d):
+        each update then discards at most d eps^2 = tau^2 ||Y_B||^2, and over a
+        stream cut into blocks the squared error stays within tau^2 ||X||^2, the
+        argument of App. D with the block in place of the slice. Alg. 4 runs on
+        the block tensor (its block mode is carried along like the slice modes,
+        so the residual Gram of mode k sums over all b slices), and the streaming
+        mode takes block_isvd. With b = 1 this is update().
+        """
+        yb = np.asarray(yb, dtype=np.float64)
+        d = self.d
+        shape = tuple(u.shape[0] for u in self.U[:-1])
+        if yb.ndim != d or yb.shape[:-1] != shape or yb.shape[-1] < 1:
+            raise ValueError("block shape mismatch")
+        b = yb.shape[-1]
+        ynorm = float(np.linalg.norm(yb))
+        if not math.isfinite(ynorm):
+            raise ValueError("non-finite block")
+        eps = self.tau * ynorm / math.sqrt(d)
+        c_k, d_k, v_k = self.C, yb, self.V
+        rec = dict(eps=eps, ynorm=ynorm, b=b, e_norm=[], grew=[], r_new=[])
+        delta2 = 0.0
+        for k in range(d - 1):
+            u_new, c_k, d_k, v_k, info = non_streaming_update(
+                k, self.U[k], c_k, d_k, v_k, eps, reorth=self.reorth)
+            self.U[k] = u_new
+            delta2 += info["delta2"]
+            rec["e_norm"].append(info["e_norm"])
+            rec["grew"].append(info["grew"])
+            rec["r_new"].append(info["r_new"])
+        r_sp = c_k.shape[:-1]
+        bmat = unfold(d_k, d - 1).T  # R x b: column j is vec of slice j's partial core
+        vmat = unfold(v_k, d - 1).T
+        ud_old = self.U[-1]
+        n_d = ud_old.shape[0]
+        ud_new, s_new, v_new, info = block_isvd(ud_old, self.S, vmat, bmat, eps,
+                                                eps_m=self.eps_m)
+        r_d_new = s_new.shape[0]
+        v_tensor = fold(v_new.T, d - 1, r_sp + (r_d_new,))
+        if self.core_update == "literal":
+            m = ud_new[:n_d, :].T @ ud_old
+            c_new = ttm(c_k, m, d - 1) + ttm(d_k, ud_new[n_d:n_d + b, :].T, d - 1)
+        else:
+            c_new = ttm(v_tensor, np.diag(s_new), d - 1)
+        delta2 += info["tail"]
+        self.C, self.V, self.S = c_new, v_tensor, s_new
+        self.U[-1] = ud_new
+        self.xnorm2 += ynorm * ynorm
+        self.disc += delta2
+        rec.update(ell=info["ell"], lam=info["lam"], tail=info["tail"], qr=info["qr"],
+                   orth_check=info["orth_check"], delta2=delta2, ranks=self.ranks)
         self.history.append(rec)
         return rec
