@@ -202,6 +202,23 @@ int st_init(st_handle *h, const float *x0, int64_t n_init);
  * call that found it returns ST_ESOLVER without doing its own work. */
 int st_update(st_handle *h, const float *y);
 
+/* Block update: b slices at once (the paper names processing several slices
+ * per update as future work, Sec. 6). y holds b slices, device float32,
+ * column-major n_1 x ... x n_{d-1} x b (slices in stream order). The
+ * per-update tolerance is the block's, eps = tau ||Y_B|| / sqrt(d), which keeps
+ * the certified bound of App. D within tau (each update discards at most
+ * tau^2 ||Y_B||^2). Alg. 4 runs on the block tensor (the residual Gram of mode k
+ * sums over all b slices); the streaming mode generalises Alg. 3: both
+ * Gram-Schmidt passes on every slice's core coordinates, the residual block's
+ * directions kept by the TruncatedSVD of Alg. 1 (eigenpairs of E^T E, tail rule
+ * against eps^2), the dense middle matrix [[diag S, 0], [P^T, W L^1/2]] with
+ * the orthogonality check of [V Q] and its QR fix, and its SVD by one-sided
+ * Jacobi. b = 1 is st_update. Literal core form only. n_d grows by b; st_stats
+ * then reports, per block, q = the norm of the discarded residual directions.
+ * Errors: ST_EINVAL (b < 1, factored core form), the errors of st_update; the
+ * decomposition is unchanged on error, as for st_update. */
+int st_update_block(st_handle *h, const float *y, int64_t b);
+
 /* Current ranks r_1..r_d (ranks[0..d-1]) of the Tucker decomposition
  * X ~ C x_1 U_1 ... x_d U_d (Sec. 2.2) and the number of slices n_d seen (the
  * row count of U_d, Alg. 5). Host counters only: no synchronisation, so it

@@ -43,8 +43,8 @@ STATUS_NAMES = {
     ST_ECAPACITY: "ST_ECAPACITY", ST_ESOLVER: "ST_ESOLVER",
 }
 
-EXPORTED = ["st_create", "st_init", "st_update", "st_ranks", "st_core", "st_factor",
-            "st_sv", "st_recon_error", "st_stats", "st_reconstruct_slice",
+EXPORTED = ["st_create", "st_init", "st_update", "st_update_block", "st_ranks", "st_core",
+            "st_factor", "st_sv", "st_recon_error", "st_stats", "st_reconstruct_slice",
             "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile", "st_aux_v",
             "st_tucker_workspace", "st_tucker_fwd", "st_tucker_bwd", "st_ttm_noalloc"]
 ST_RECONSTRUCT, ST_PROJECT = 0, 1
@@ -126,6 +126,7 @@ _sig = {
     "st_create": (C.c_int, [C.POINTER(st_config), C.POINTER(_h)]),
     "st_init": (C.c_int, [_h, C.c_void_p, C.c_int64]),
     "st_update": (C.c_int, [_h, C.c_void_p]),
+    "st_update_block": (C.c_int, [_h, C.c_void_p, C.c_int64]),
     "st_ranks": (C.c_int, [_h, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "st_core": (C.c_int, [_h, C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_int]),
     "st_aux_v": (C.c_int, [_h, C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_int]),
@@ -163,6 +164,7 @@ for _name, (_res, _args) in _sig.items():
 st_create = lib.st_create
 st_init = lib.st_init
 st_update = lib.st_update
+st_update_block = lib.st_update_block
 st_ranks = lib.st_ranks
 st_core = lib.st_core
 st_factor = lib.st_factor
@@ -322,6 +324,10 @@ class StreamingTucker:
 
     def update(self, y):
         self._call(st_update, self._dev(y, self.slice_elems))
+
+    def update_block(self, y, b):
+        """b slices at once (y: b slices back to back, the block mode last)."""
+        self._call(st_update_block, self._dev(y, self.slice_elems * int(b)), int(b))
 
     @property
     def ranks(self):

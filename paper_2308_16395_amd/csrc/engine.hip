@@ -98,6 +98,7 @@ struct st_handle {
   Prec prec = Prec::FP32;
   double orth_tol = 1e-12;
   int64_t qr_total = 0;  // QR fixes applied since init
+  int64_t blk = 1;       // slices in the update being processed (block updates)
   double guard_rel = 0.0;
   int64_t max_rank_d = 0;
   hipStream_t stream = nullptr;
@@ -135,6 +136,7 @@ struct st_handle {
   int v0cur = 0;
   DBuf<double> Mf[2], Gf[2];  // M and G0 = V0^T V0 (r_d x r_d)
   DBuf<double> tvec, wvec, e1buf, tmp64, qrw, qrg, qvte;
+  DBuf<double> bV, bE, bQ, bC, bsm;  // block updates: V at new rows, E, Q, FP64 core, small
   DBuf<int> qstat;
   DBuf<float> tmp32;
 
@@ -246,8 +248,11 @@ struct st_handle {
     for (int k = 0; k < upto; ++k) p_ *= rr[k];
     return p_;
   }
+  // product of the slice dims from mode `from` on, times the number of slices
+  // in the update being processed (blk = 1 except inside a block update, whose
+  // block mode is carried along the slice-mode chain like another slice mode)
   int64_t nprod(int from) const {
-    int64_t p_ = 1;
+    int64_t p_ = blk;
     for (int k = from; k < m; ++k) p_ *= n[k];
     return p_;
   }
@@ -477,7 +482,12 @@ struct st_handle {
   }
   int exact_coords(const float *y, const double **dout);
   int do_init(const float *x0, int64_t n_init);
-  int do_update(const float *y);
+  int do_update(const float *y, int64_t b = 1);
+  int stream_block(const RowMap &map, const double *Dm, int64_t b, int64_t Rold, int64_t Rnew,
+                   double eps, st_slice_stats &stt, const int64_t *rn, double delta2,
+                   double ynorm2, double ms_modes, clk::time_point t0);
+  hipError_t chunk_tn(const double *X, int64_t ldx, const double *Y, int64_t ldy, int64_t R,
+                      int p, int q, double *out);
   int stream_factored(const RowMap &map, const double *dvec, int64_t Rold, int64_t Rnew,
                       double eps, st_slice_stats &stt, int &grow, double &q2, int64_t &c,
                       int &v0next, bool exact_d, const float *y);
@@ -671,16 +681,32 @@ int st_handle::exact_coords(const float *y, const double **dout) {
 // ---------------------------------------------------------------------------
 // Alg. 5.
 // ---------------------------------------------------------------------------
-int st_handle::do_update(const float *y) {
+int st_handle::do_update(const float *y, int64_t bsz) {
   const auto t0 = clk::now();
   if (!inited) return fail(ST_ESTATE, "update before init");
   if (y == nullptr) return fail(ST_EINVAL, "null slice");
+  if (bsz < 1) return fail(ST_EINVAL, "block of %lld slices", (long long)bsz);
+  if (bsz > 1 && factored)
+    return fail(ST_EINVAL, "block updates take the literal core form (ST_CORE_LITERAL)");
   const int d = m + 1;
   st_slice_stats stt{};
   int64_t rn[ST_MAX_MODES];
   for (int k = 0; k < m; ++k) rn[k] = r[k];
-  hipError_t e = ensure_pinned(2 * (size_t)std::max<int64_t>(rd + 2, 64) + 64);
+  // (a block update also reads back b eigenvalues and V^T Q, Q^T Q: b (r_d + b))
+  hipError_t e = ensure_pinned(2 * (size_t)std::max<int64_t>(rd + 2, 64) + 64 +
+                               (size_t)(bsz * (rd + bsz) + 4 * bsz));
   if (e != hipSuccess) return hipfail(e, "pinned buffer");
+  // the slice-mode chain below runs on all bsz slices at once (nprod includes blk)
+  struct BlkScope {
+    int64_t &b;
+    ~BlkScope() { b = 1; }
+  } blk_scope{blk};
+  blk = bsz;
+  if (bsz > 1) {
+    e = D[0].ensure((size_t)(NY * bsz));
+    if (e == hipSuccess) e = D[1].ensure((size_t)(NY * bsz));
+    if (e != hipSuccess) return hipfail(e, "block buffers");
+  }
 
   std::vector<double> desc;
   const void *Din = y;
@@ -854,6 +880,17 @@ int st_handle::do_update(const float *y) {
   if (!din64) return fail(ST_EINVAL, "slice has no slice modes");
   const double *dvec = static_cast<const double *>(Din);  // (replaced by exact coordinates
                                                           // when the ISVD is refined)
+  if (bsz > 1) {
+    // the block form of Alg. 3 decides on FP64-product coordinates only
+    if (!exact_d) {
+      const double *dex = nullptr;
+      rc = exact_coords(y, &dex);
+      if (rc != ST_OK) return rc;
+      dvec = dex;
+      stt.refined_isvd = 1;
+    }
+    return stream_block(map, dvec, bsz, Rold, Rnew, eps, stt, rn, delta2, ynorm2, ms_modes, t0);
+  }
   if (factored) {
     int growf = 0, v0next = v0cur;
     double q2f = 0.0;
@@ -1459,6 +1496,262 @@ int st_handle::qr_fix(const double *Gtop, int rdi, const double *vte, const doub
   return ST_OK;
 }
 
+// out (p x q) = X^T Y for column-major X (R x p, ld ldx) and Y (R x q, ld ldy):
+// library GEMMs over row chunks into separate partials, summed in a fixed order.
+hipError_t st_handle::chunk_tn(const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                               int64_t R, int p_, int q_, double *out) {
+  const size_t pq = (size_t)p_ * q_;
+  if (pq == 0) return hipSuccess;
+  const int64_t max_parts = std::max<int64_t>(1, std::min<int64_t>(1024, (8 << 20) / (int64_t)pq));
+  const int64_t ch = std::max<int64_t>(2048, (R + max_parts - 1) / max_parts);
+  const int64_t nfull = R / ch, tail = R - nfull * ch;
+  const int64_t nb = nfull + (tail > 0 ? 1 : 0);
+  if (nb == 0) return hipErrorInvalidValue;
+  hipError_t e = tmp64.ensure((size_t)nb * pq);
+  if (e != hipSuccess) return e;
+  const double one = 1.0, zero = 0.0;
+  rocblas_status bs = rocblas_status_success;
+  if (nfull > 0)
+    bs = rocblas_dgemm_strided_batched(
+        rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)p_, (rocblas_int)q_,
+        (rocblas_int)ch, &one, X, (rocblas_int)ldx, (rocblas_stride)ch, Y, (rocblas_int)ldy,
+        (rocblas_stride)ch, &zero, tmp64.p, (rocblas_int)p_, (rocblas_stride)pq,
+        (rocblas_int)nfull);
+  if (bs == rocblas_status_success && tail > 0)
+    bs = rocblas_dgemm(rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)p_,
+                       (rocblas_int)q_, (rocblas_int)tail, &one, X + nfull * ch, (rocblas_int)ldx,
+                       Y + nfull * ch, (rocblas_int)ldy, &zero, tmp64.p + (size_t)nfull * pq,
+                       (rocblas_int)p_);
+  if (bs != rocblas_status_success) return hipErrorUnknown;
+  return launch_batch_sum(tmp64.p, (int)nb, (int64_t)pq, out, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 3 for a block of b slices (the paper's Sec. 6 future work), literal core.
+// Dm (R_new x b, FP64) holds the slices' core coordinates. Both Gram-Schmidt
+// passes run on all b columns (P1 = V^T Dm, E = Dm - V P1, P2 = V^T E,
+// E -= V P2); the residual block's kept directions follow the TruncatedSVD of
+// Alg. 1 on E (eigenpairs of E^T E, tail rule against eps^2); Q = E W_l L_l^-1/2
+// extends V; the middle matrix [[diag S, 0], [P^T, W_l L_l^1/2]] is dense, so its
+// SVD is one-sided Jacobi (k_dense.hip), after the QR fix of the orthogonality
+// check when [V Q] is not orthonormal to eps_m. Then V~ = [V Q] V'',
+// C~ = [C, Dm] U'' and U~_d = blockdiag(U_d, I_b) U''; commits like the
+// single-slice form.
+// ---------------------------------------------------------------------------
+int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int64_t Rold,
+                            int64_t Rnew, double eps, st_slice_stats &stt, const int64_t *rn,
+                            double delta2, double ynorm2, double ms_modes,
+                            clk::time_point t0) {
+  const int rdi = (int)rd, bi = (int)b;
+  const int n2 = rdi + bi;  // rows of the middle matrix (and its padded order)
+  const int nxt = cur ^ 1;
+  const size_t nn2 = (size_t)n2 * n2;
+  hipError_t e = hipSuccess;
+  tic();
+  // V at the new row layout (the padded rows are zero)
+  const double *Vn = V[cur].p;
+  if (!map.identity) {
+    e = bV.ensure((size_t)Rnew * std::max(rdi, 1));
+    if (e == hipSuccess) e = launch_remap_rows(V[cur].p, Rold, map, Rnew, rdi, bV.p, stream);
+    Vn = bV.p;
+  }
+  // small buffers: P1, P2, P (rd x b each), GE (b x b), Wsc (b x b), VQ (rd x b),
+  // QQ (b x b), VtV (rd x rd), then G, K, W, Rpad, sig for the dense part
+  const size_t rb_ = (size_t)rdi * bi, bb = (size_t)bi * bi;
+  const size_t off_p2 = rb_, off_p = 2 * rb_, off_ge = 3 * rb_, off_wsc = off_ge + bb,
+               off_vq = off_wsc + bb, off_qq = off_vq + rb_, off_vtv = off_qq + bb,
+               off_g = off_vtv + (size_t)rdi * rdi, off_k = off_g + nn2, off_w = off_k + nn2,
+               off_r = off_w + nn2, off_sig = off_r + nn2, off_ge2 = off_sig + n2 + bi,
+               off_gw = off_ge2 + bb, nsmall = off_gw + bb;
+  if (e == hipSuccess) e = bsm.ensure(nsmall);
+  if (e == hipSuccess) e = bE.ensure((size_t)Rnew * bi);
+  if (e == hipSuccess) e = qstat.ensure(2);
+  if (e != hipSuccess) return hipfail(e, "block buffers");
+  double *P1 = bsm.p, *P2 = bsm.p + off_p2, *Pv = bsm.p + off_p, *GE = bsm.p + off_ge,
+         *Wsc = bsm.p + off_wsc, *VQ = bsm.p + off_vq, *QQ = bsm.p + off_qq,
+         *VtV = bsm.p + off_vtv, *G = bsm.p + off_g, *K = bsm.p + off_k, *Wj = bsm.p + off_w,
+         *Rp = bsm.p + off_r, *sig = bsm.p + off_sig, *GE2 = bsm.p + off_ge2,
+         *GW = bsm.p + off_gw;
+  const double one = 1.0, mone = -1.0, zero = 0.0;
+  rocblas_status bs = rocblas_status_success;
+  // two Gram-Schmidt passes on all b columns
+  if (rdi > 0) {
+    e = chunk_tn(Vn, Rnew, Dm, Rnew, Rnew, rdi, bi, P1);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bE.p, Dm, (size_t)Rnew * bi * sizeof(double), hipMemcpyDeviceToDevice,
+                         stream);
+    if (e == hipSuccess)
+      bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew,
+                         bi, rdi, &mone, Vn, (rocblas_int)Rnew, P1, rdi, &one, bE.p,
+                         (rocblas_int)Rnew);
+    if (e == hipSuccess && bs == rocblas_status_success)
+      e = chunk_tn(Vn, Rnew, bE.p, Rnew, Rnew, rdi, bi, P2);
+    if (e == hipSuccess && bs == rocblas_status_success)
+      bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew,
+                         bi, rdi, &mone, Vn, (rocblas_int)Rnew, P2, rdi, &one, bE.p,
+                         (rocblas_int)Rnew);
+    if (e == hipSuccess) e = launch_vadd(P1, P2, (int64_t)rb_, Pv, stream);
+  } else {
+    e = hipMemcpyAsync(bE.p, Dm, (size_t)Rnew * bi * sizeof(double), hipMemcpyDeviceToDevice,
+                       stream);
+  }
+  if (bs != rocblas_status_success) return fail(ST_EHIP, "block projection GEMM failed");
+  // TruncatedSVD of the residual block (Alg. 1 on E^T): eigenpairs of E^T E by
+  // one-sided Jacobi (E^T E is positive semidefinite: its singular values are
+  // its eigenvalues, its right singular vectors the eigenvectors)
+  if (e == hipSuccess) e = chunk_tn(bE.p, Rnew, bE.p, Rnew, Rnew, bi, bi, GE);
+  if (e == hipSuccess) e = hipMemsetAsync(qstat.p, 0, 2 * sizeof(int), stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(GE2, GE, bb * sizeof(double), hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess) e = launch_pad_upper(nullptr, 0, bi, Rp, stream);
+  if (e == hipSuccess) e = launch_jacobi_svd(GE2, bi, Wj, 60, qstat.p, stream);
+  // (sorted eigenvectors into GW; the left vectors, unused, into K)
+  if (e == hipSuccess) e = launch_jacobi_finish(GE2, Wj, Rp, bi, K, GW, sig, sig + bi, stream);
+  toc(ST_K_ISVD, 6.0 * Rnew * rdi * b + 2.0 * Rnew * b * b,
+      8.0 * (2.0 * Rnew * rdi + 4.0 * Rnew * b));
+  if (e == hipSuccess) e = launch_gather3(hpin_dev, sig, bi, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
+  int st2[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(st2, qstat.p, sizeof(st2), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "block residual");
+  settle();
+  if (st2[0] != 0) return fail(ST_ESOLVER, "block residual eigensolver did not converge");
+  std::vector<double> lam_asc(bi), desc;
+  for (int i = 0; i < bi; ++i) {
+    if (!std::isfinite(hpin[i])) return fail(ST_ENONFINITE, "non-finite block residual");
+    lam_asc[bi - 1 - i] = hpin[i];
+  }
+  int64_t ell64 = 0;
+  double tail = 0.0;
+  rank_rule(lam_asc.data(), bi, eps, ell64, tail, desc);
+  const int ell = (int)ell64;
+  const int c = rdi + ell;
+  stt.q = std::sqrt(std::max(tail, 0.0));
+  stt.isvd_ignored = ell < bi ? 1 : 0;
+  stt.orth_check = 0.0;
+  stt.qr_fired = 0;
+  if (max_rank_d > 0 && c > max_rank_d)
+    return fail(ST_ECAPACITY, "streaming rank %lld exceeds the cap", (long long)c);
+  // buffers of the new state
+  e = U2.ensure(nn2);
+  if (e == hipSuccess) e = V2.ensure(nn2);
+  if (e == hipSuccess) e = S[nxt].ensure((size_t)n2);
+  if (e == hipSuccess) e = V[nxt].ensure((size_t)Rnew * std::max(c, 1));
+  if (e == hipSuccess) e = C[nxt].ensure((size_t)Rnew * std::max(c, 1));
+  if (e == hipSuccess) e = bQ.ensure((size_t)Rnew * std::max(ell, 1));
+  int64_t ldn = ud_ld[nxt];
+  if (e == hipSuccess && (ldn < nd + b || Ud[nxt].cap < (size_t)ldn * c)) {
+    ldn = std::max<int64_t>(ud_ld[cur], round_up(nd + b, 64));
+    e = Ud[nxt].ensure((size_t)ldn * std::max(c, 1));
+  }
+  if (e != hipSuccess) return hipfail(e, "streaming buffers");
+  ud_ld[nxt] = ldn;
+  tic();
+  if (ell > 0) {
+    // Q = E W_l L_l^{-1/2}, and the orthogonality of [V Q]: V^T Q and Q^T Q - I
+    e = launch_scale_cols_rsqrt(GW, bi, bi, ell, sig, Wsc, stream);
+    if (e == hipSuccess)
+      bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew,
+                         ell, bi, &one, bE.p, (rocblas_int)Rnew, Wsc, bi, &zero, bQ.p,
+                         (rocblas_int)Rnew);
+    if (bs != rocblas_status_success) return fail(ST_EHIP, "block basis GEMM failed");
+    if (e == hipSuccess && rdi > 0) e = chunk_tn(Vn, Rnew, bQ.p, Rnew, Rnew, rdi, ell, VQ);
+    if (e == hipSuccess) e = chunk_tn(bQ.p, Rnew, bQ.p, Rnew, Rnew, ell, ell, QQ);
+    if (e == hipSuccess)
+      e = launch_gather3(hpin_dev, VQ, rdi * ell, 0, QQ, ell * ell, rdi * ell, nullptr, 0, 0,
+                         stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hipfail(e, "block orthogonality check");
+    settle();
+    double orth = 0.0;
+    for (int i = 0; i < rdi * ell; ++i) orth = std::max(orth, std::fabs(hpin[i]));
+    for (int j = 0; j < ell; ++j)
+      for (int i = 0; i < ell; ++i)
+        orth = std::max(orth, std::fabs(hpin[rdi * ell + i + ell * j] - (i == j ? 1.0 : 0.0)));
+    stt.orth_check = orth;
+    stt.qr_fired = orth > orth_tol ? 1 : 0;
+  }
+  // middle matrix (zero-padded to n2 x n2), with the QR fix when the check fired
+  e = launch_block_k(S[cur].p, Pv, rdi, bi, GW, bi, sig, ell, K, stream);
+  if (e == hipSuccess && stt.qr_fired) {
+    if (rdi > 0) e = chunk_tn(Vn, Rnew, Vn, Rnew, Rnew, rdi, rdi, VtV);
+    if (e == hipSuccess) e = launch_gram_block_fill(VtV, rdi, VQ, QQ, ell, G, stream);
+    if (e == hipSuccess) e = launch_chol_upper(G, c, qstat.p, stream);
+    if (e == hipSuccess) e = launch_right_mul_rt(K, n2, G, c, stream);
+    if (e == hipSuccess) e = launch_pad_upper(G, c, n2, Rp, stream);
+  } else if (e == hipSuccess) {
+    e = hipMemsetAsync(qstat.p, 0, 2 * sizeof(int), stream);
+    if (e == hipSuccess) e = launch_pad_upper(nullptr, 0, n2, Rp, stream);
+  }
+  if (e == hipSuccess) e = launch_jacobi_svd(K, n2, Wj, 60, qstat.p, stream);
+  if (e == hipSuccess) e = launch_jacobi_finish(K, Wj, Rp, n2, U2.p, V2.p, S[nxt].p, sig, stream);
+  toc(ST_K_SVD, 40.0 * (double)n2 * n2 * n2, 8.0 * 4.0 * nn2);
+  if (e == hipSuccess) e = hipMemcpyAsync(st2, qstat.p, sizeof(st2), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "block middle matrix");
+  settle();
+  if (st2[0] == 1) return fail(ST_ESOLVER, "QR fix: the Gram of [V Q] is not positive definite");
+  if (st2[0] == 2) return fail(ST_ESOLVER, "block middle matrix: Jacobi SVD did not converge");
+  // V~ = V V''(0:rd, :) + Q V''(rd:c, :)
+  tic();
+  if (rdi > 0)
+    bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew, c,
+                       rdi, &one, Vn, (rocblas_int)Rnew, V2.p, n2, &zero, V[nxt].p,
+                       (rocblas_int)Rnew);
+  if (bs == rocblas_status_success && ell > 0)
+    bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew, c,
+                       ell, &one, bQ.p, (rocblas_int)Rnew, V2.p + rdi, n2,
+                       rdi > 0 ? &one : &zero, V[nxt].p, (rocblas_int)Rnew);
+  toc(ST_K_ROT_V, 2.0 * Rnew * (double)c * c, 8.0 * Rnew * (rdi + ell + c));
+  if (bs != rocblas_status_success) return fail(ST_EHIP, "block V rotation failed");
+  // C~ = C U''(0:rd, :) + Dm U''(rd:rd+b, :), formed in FP64 and rounded once
+  tic();
+  e = bC.ensure((size_t)Rnew * std::max(c, std::max(rdi, 1)) * 2);
+  if (e != hipSuccess) return hipfail(e, "block core buffer");
+  double *Cd = bC.p, *Cn = bC.p + (size_t)Rnew * std::max(c, std::max(rdi, 1));
+  if (rdi > 0) e = launch_remap_rows_f32(C[cur].p, Rold, map, Rnew, rdi, Cd, stream);
+  if (e == hipSuccess && rdi > 0)
+    bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew, c,
+                       rdi, &one, Cd, (rocblas_int)Rnew, U2.p, n2, &zero, Cn, (rocblas_int)Rnew);
+  if (e == hipSuccess && bs == rocblas_status_success)
+    bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew, c,
+                       bi, &one, Dm, (rocblas_int)Rnew, U2.p + rdi, n2, rdi > 0 ? &one : &zero,
+                       Cn, (rocblas_int)Rnew);
+  if (e == hipSuccess && bs == rocblas_status_success)
+    e = launch_f64_to_f32(Cn, Rnew * c, C[nxt].p, stream);
+  toc(ST_K_ROT_C, 2.0 * Rnew * (double)(rdi + b) * c, 4.0 * Rold * rdi + 8.0 * Rnew * b + 4.0 * Rnew * c);
+  if (bs != rocblas_status_success) return fail(ST_EHIP, "block core GEMM failed");
+  if (e != hipSuccess) return hipfail(e, "block core update");
+  tic();
+  e = launch_ud_update_block(Ud[cur].p, ud_ld[cur], nd, rdi, bi, U2.p, n2, c, Ud[nxt].p, ldn,
+                             stream);
+  toc(ST_K_UD, 2.0 * nd * (double)rd * c, 8.0 * ((double)nd * rd + (nd + b) * c));
+  if (e == hipSuccess) e = ensure_hS((size_t)c);
+  if (e == hipSuccess)
+    e = launch_gather3(hS_dev, S[nxt].p, c, 0, nullptr, 0, 0, nullptr, 0, 0, stream);
+  if (e != hipSuccess) return hipfail(e, "streaming factor update");
+  // ---- commit ----
+  snapshot();
+  s_pending = c;
+  for (int k = 0; k < m; ++k) r[k] = rn[k];
+  rd = c;
+  nd += b;
+  cur = nxt;
+  xnorm2 += ynorm2;
+  delta2 += tail;
+  disc += delta2;
+  stt.ynorm = std::sqrt(ynorm2);
+  stt.eps = eps;
+  stt.delta2 = delta2;
+  stt.ms_modes = ms_modes;
+  stt.ms_total = ms_since(t0);
+  stt.ms_isvd = stt.ms_total - ms_modes;
+  qr_total += stt.qr_fired;
+  stt.qr_total = qr_total;
+  stats = stt;
+  return ST_OK;
+}
+
 // V0 M diag(S) (S not null: the core C_(d)^T) or V0 M (V) into out64 (R x r_d).
 hipError_t st_handle::factored_product(const double *S_or_null, double *out64) {
   const int64_t R = rprod(r, m);
@@ -1570,6 +1863,11 @@ void st_handle::destroy() {
   e1buf.release();
   tmp64.release();
   qrw.release();
+  bV.release();
+  bE.release();
+  bQ.release();
+  bC.release();
+  bsm.release();
   qrg.release();
   qvte.release();
   qstat.release();
@@ -1720,7 +2018,13 @@ int st_init(st_handle *h, const float *x0, int64_t n_init) {
 int st_update(st_handle *h, const float *y) {
   if (!h) return ST_EINVAL;
   (void)hipSetDevice(h->device);
-  return h->do_update(y);
+  return h->do_update(y, 1);
+}
+
+int st_update_block(st_handle *h, const float *y, int64_t b) {
+  if (!h) return ST_EINVAL;
+  (void)hipSetDevice(h->device);
+  return h->do_update(y, b);
 }
 
 int st_ranks(const st_handle *h, int64_t *ranks, int64_t *n_d) {

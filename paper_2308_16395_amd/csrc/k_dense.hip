@@ -216,4 +216,159 @@ hipError_t launch_jacobi_finish(const double *A, const double *W, const double *
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Block form of the streaming update (b new slices at once): small kernels
+// around the dense middle matrix.
+// ---------------------------------------------------------------------------
+
+// out (rows x ell) = W(:, 0:ell) scaled by lam_j^{-1/2} per column (W: ld ldw)
+__global__ void scale_cols_rsqrt_kernel(const double *W, int ldw, int rows, int ell,
+                                        const double *lam, double *out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ell) return;
+  const int i = idx % rows, j = idx / rows;
+  out[i + (size_t)rows * j] = W[i + (size_t)ldw * j] / sqrt(lam[j]);
+}
+
+hipError_t launch_scale_cols_rsqrt(const double *W, int ldw, int rows, int ell, const double *lam,
+                                   double *out, hipStream_t s) {
+  if (rows * ell <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_cols_rsqrt_kernel, dim3((unsigned)((rows * ell + 255) / 256)),
+                     dim3(256), 0, s, W, ldw, rows, ell, lam, out);
+  return hipGetLastError();
+}
+
+// The block middle matrix, zero-padded to n x n (n = rd + b):
+//   K = [[diag(S), 0], [P^T, W_l Lambda_l^{1/2}]]   ((rd + b) x (rd + l))
+// P is rd x b (ld rd), W b x b (ld ldw), lam the eigenvalues (descending).
+__global__ void block_k_kernel(const double *S, const double *P, int rd, int b, const double *W,
+                               int ldw, const double *lam, int ell, double *K) {
+  const int n = rd + b;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx % n, j = idx / n;
+  double v = 0.0;
+  if (i < rd) {
+    if (j == i) v = S[i];
+  } else if (j < rd) {
+    v = P[j + (size_t)rd * (i - rd)];
+  } else if (j < rd + ell) {
+    v = W[(i - rd) + (size_t)ldw * (j - rd)] * sqrt(lam[j - rd]);
+  }
+  K[idx] = v;
+}
+
+hipError_t launch_block_k(const double *S, const double *P, int rd, int b, const double *W, int ldw,
+                          const double *lam, int ell, double *K, hipStream_t s) {
+  const int n = rd + b;
+  hipLaunchKernelGGL(block_k_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, S,
+                     P, rd, b, W, ldw, lam, ell, K);
+  return hipGetLastError();
+}
+
+// G (c x c, c = rd + l) = [[Gtop, VQ], [VQ^T, QQ]]: the Gram of [V Q]
+__global__ void gram_block_fill_kernel(const double *Gtop, int rd, const double *VQ,
+                                       const double *QQ, int ell, double *G) {
+  const int c = rd + ell;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  const int i = idx % c, j = idx / c;
+  double v;
+  if (i < rd && j < rd) v = Gtop[i + (size_t)rd * j];
+  else if (i < rd) v = VQ[i + (size_t)rd * (j - rd)];
+  else if (j < rd) v = VQ[j + (size_t)rd * (i - rd)];
+  else v = QQ[(i - rd) + (size_t)ell * (j - rd)];
+  G[idx] = v;
+}
+
+hipError_t launch_gram_block_fill(const double *Gtop, int rd, const double *VQ, const double *QQ,
+                                  int ell, double *G, hipStream_t s) {
+  const int c = rd + ell;
+  hipLaunchKernelGGL(gram_block_fill_kernel, dim3((unsigned)((c * c + 255) / 256)), dim3(256), 0,
+                     s, Gtop, rd, VQ, QQ, ell, G);
+  return hipGetLastError();
+}
+
+// In place on K (n x n, ld n): K(:, 0:c) <- K(:, 0:c) R^T for R upper (c x c, ld c);
+// one thread per row (each row of K is read before it is written).
+__global__ void right_mul_rt_kernel(double *K, int n, const double *R, int c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // (K R^T)(i, j) = sum_{k >= j} K(i, k) R(j, k): ascending j reads only columns >= j
+  for (int j = 0; j < c; ++j) {
+    double acc = 0.0;
+    for (int k = j; k < c; ++k) acc += K[i + (size_t)n * k] * R[j + (size_t)c * k];
+    K[i + (size_t)n * j] = acc;
+  }
+}
+
+hipError_t launch_right_mul_rt(double *K, int n, const double *R, int c, hipStream_t s) {
+  hipLaunchKernelGGL(right_mul_rt_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, K, n, R,
+                     c);
+  return hipGetLastError();
+}
+
+// Rpad (n x n) = [[R, 0], [0, I]] for R (c x c, ld c), or the identity (R null)
+__global__ void pad_upper_kernel(const double *R, int c, int n, double *Rp) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx % n, j = idx / n;
+  double v = (i == j) ? 1.0 : 0.0;
+  if (R && i < c && j < c) v = R[i + (size_t)c * j];
+  Rp[idx] = v;
+}
+
+hipError_t launch_pad_upper(const double *R, int c, int n, double *Rp, hipStream_t s) {
+  hipLaunchKernelGGL(pad_upper_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, R, c,
+                     n, Rp);
+  return hipGetLastError();
+}
+
+// U~_d ((nd + b) x c) = [[U_d, 0], [0, I_b]] U'' with U'' ((rd + b) x c, ld ldu2)
+__global__ void ud_update_block_kernel(const double *Ud, int64_t ldo, int64_t nd, int rd, int b,
+                                       const double *U2, int ldu2, int c, double *Un,
+                                       int64_t ldn) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = nd + b;
+  if (idx >= rows * c) return;
+  const int64_t row = idx % rows;
+  const int col = (int)(idx / rows);
+  const double *u2c = U2 + (size_t)ldu2 * col;
+  double acc;
+  if (row < nd) {
+    acc = 0.0;
+    for (int k = 0; k < rd; ++k) acc += Ud[row + ldo * k] * u2c[k];
+  } else {
+    acc = u2c[rd + (row - nd)];
+  }
+  Un[row + ldn * col] = acc;
+}
+
+hipError_t launch_ud_update_block(const double *Ud, int64_t ldo, int64_t nd, int rd, int b,
+                                  const double *U2, int ldu2, int c, double *Un, int64_t ldn,
+                                  hipStream_t s) {
+  const int64_t total = (nd + b) * c;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ud_update_block_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     s, Ud, ldo, nd, rd, b, U2, ldu2, c, Un, ldn);
+  return hipGetLastError();
+}
+
+// dst (Rn x cols, FP64) = src (FP32, old row layout, ld ld_src) through the row map
+__global__ void remap_rows_f32_kernel(const float *src, int64_t ld_src, RowMap map, int64_t Rn,
+                                      int cols, double *dst) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= Rn) return;
+  const int64_t o = map_new_to_old(map, row);
+  for (int j = 0; j < cols; ++j) dst[row + Rn * j] = (o >= 0) ? (double)src[o + ld_src * j] : 0.0;
+}
+
+hipError_t launch_remap_rows_f32(const float *src, int64_t ld_src, RowMap map, int64_t Rn, int cols,
+                                 double *dst, hipStream_t s) {
+  if (Rn <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(remap_rows_f32_kernel, dim3((unsigned)((Rn + 255) / 256)), dim3(256), 0, s,
+                     src, ld_src, map, Rn, cols, dst);
+  return hipGetLastError();
+}
+
 }  // namespace st

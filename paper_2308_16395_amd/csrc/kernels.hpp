@@ -109,6 +109,20 @@ hipError_t launch_jacobi_svd(double *A, int n, double *W, int max_sweeps, int *s
 hipError_t launch_jacobi_finish(const double *A, const double *W, const double *R, int n,
                                 double *U2, double *V2, double *Snew, double *sig,
                                 hipStream_t s);
+// Block updates (k_dense.hip): see the kernels for the layouts.
+hipError_t launch_scale_cols_rsqrt(const double *W, int ldw, int rows, int ell, const double *lam,
+                                   double *out, hipStream_t s);
+hipError_t launch_block_k(const double *S, const double *P, int rd, int b, const double *W, int ldw,
+                          const double *lam, int ell, double *K, hipStream_t s);
+hipError_t launch_gram_block_fill(const double *Gtop, int rd, const double *VQ, const double *QQ,
+                                  int ell, double *G, hipStream_t s);
+hipError_t launch_right_mul_rt(double *K, int n, const double *R, int c, hipStream_t s);
+hipError_t launch_pad_upper(const double *R, int c, int n, double *Rp, hipStream_t s);
+hipError_t launch_ud_update_block(const double *Ud, int64_t ldo, int64_t nd, int rd, int b,
+                                  const double *U2, int ldu2, int c, double *Un, int64_t ldn,
+                                  hipStream_t s);
+hipError_t launch_remap_rows_f32(const float *src, int64_t ld_src, RowMap map, int64_t Rn, int cols,
+                                 double *dst, hipStream_t s);
 // out[i] = sum over b < nb of part[b * n + i], in a fixed order
 hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, hipStream_t s);
 // delta = a - b (n rows) and per-block pairs (sum b * delta, sum delta^2) in

@@ -1,0 +1,120 @@
+"""GPU parity of the block update (b slices per call, st_update_block) against
+the oracle's update_block on the same float32 slices: ranks after every block,
+the number of kept residual directions, reconstructions of probe slices
+(within 1e-5 of the slice norm: the literal core is stored in FP32), the
+singular values and the certified bound; a ragged last block; the forced QR
+fix of the block orthogonality check; b = 1 against the single-slice update.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import StreamingTucker as Oracle
+from oracle import vec
+from synth import BlobStream
+from tests._parity import slices32
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(s, n, n_init, tau, bsize, precision="fp64", orth_tol=0.0, eps_m=1e-12):
+    import torch
+
+    import paper_2308_16395_amd as pkg
+
+    flat, shaped = slices32(s, n)
+    orc = Oracle(np.stack(shaped[:n_init], axis=-1), tau, eps_m=eps_m)
+    gpu = pkg.StreamingTucker(s.dims, tau, precision=precision, orth_tol=orth_tol)
+    gpu.init(torch.from_numpy(np.concatenate(flat[:n_init])).cuda(), n_init)
+    assert gpu.ranks == orc.ranks
+    worst, t, stats = 0.0, n_init, []
+    while t < n:
+        b = min(bsize, n - t)
+        y = torch.from_numpy(np.concatenate(flat[t:t + b])).cuda()
+        gpu.update_block(y, b)
+        rec = orc.update_block(np.stack(shaped[t:t + b], axis=-1))
+        st = gpu.stats()
+        stats.append((st, rec))
+        assert gpu.ranks == orc.ranks, (t, gpu.ranks, orc.ranks, rec["lam"], rec["eps"])
+        t += b
+        for probe in sorted({0, t - 1, (n_init + t) // 2}):
+            g = gpu.reconstruct_slice(probe).cpu().numpy().astype(np.float64)
+            o = vec(orc.reconstruct_slice(probe))
+            worst = max(worst, np.linalg.norm(g - o) / np.linalg.norm(shaped[probe]))
+    return gpu, orc, worst, stats
+
+
+def _check_s_and_bound(gpu, orc, rel):
+    s_gpu, s_orc = np.asarray(gpu.sv()), np.asarray(orc.S)
+    assert s_gpu.shape == s_orc.shape
+    assert np.max(np.abs(s_gpu - s_orc)) <= rel * s_orc[0], np.max(np.abs(s_gpu - s_orc))
+    bound, _ = gpu.recon_error()
+    np.testing.assert_allclose(bound, orc.recon_error_bound(), rtol=1e-3)
+    assert bound <= orc.tau
+
+
+@pytest.mark.parametrize("bsize", [3, 4])
+def test_block_updates_fp64_products(bsize):
+    s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=36, seed=21)
+    gpu, orc, worst, stats = _run(s, 36, 6, 1e-3, bsize)
+    assert worst <= 1e-5, worst
+    _check_s_and_bound(gpu, orc, 1e-9)
+    assert gpu.ranks[-1] == orc.ranks[-1] and sum(rec["ell"] for _, rec in stats) > 5
+
+
+@pytest.mark.parametrize("precision,bsize", [("fp32", 3), ("bf16x3", 5)])
+def test_block_updates_fast_forms(precision, bsize):
+    s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=36, seed=21)
+    gpu, orc, worst, _ = _run(s, 36, 6, 1e-3, bsize, precision=precision)
+    assert worst <= (1e-5 if precision == "fp32" else 1e-4), worst
+    _check_s_and_bound(gpu, orc, 1e-5)
+
+
+def test_block_updates_medium_stream():
+    """48^3 x 8 blobs, tau = 1e-4 (growth in every mode), blocks of 4."""
+    s = BlobStream((48, 48, 48), 8, 16, (3.0, 8.0), 0.5, n_slices=42, seed=41)
+    gpu, orc, worst, _ = _run(s, 42, 10, 1e-4, 4)
+    assert worst <= 1e-5, worst
+    _check_s_and_bound(gpu, orc, 1e-9)
+
+
+def test_block_qr_fix_forced():
+    s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=36, seed=21)
+    gpu, orc, worst, stats = _run(s, 36, 6, 1e-3, 3, orth_tol=1e-300, eps_m=0.0)
+    fired_gpu = [bool(st["qr_fired"]) for st, _ in stats]
+    fired_orc = [bool(rec["qr"]) for _, rec in stats]
+    assert fired_gpu == fired_orc and sum(fired_gpu) >= 5
+    assert worst <= 1e-5, worst
+    _check_s_and_bound(gpu, orc, 1e-9)
+    v = gpu.aux_v()
+    import torch
+
+    g = v.T @ v
+    assert torch.max(torch.abs(g - torch.eye(g.shape[0], device=g.device, dtype=g.dtype))) < 1e-8
+
+
+def test_block_of_one_is_update_and_factored_is_refused():
+    import torch
+
+    import paper_2308_16395_amd as pkg
+    from paper_2308_16395_amd.binding import ST_EINVAL, StError
+
+    s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=20, seed=21)
+    flat, _ = slices32(s, 20)
+    x0 = torch.from_numpy(np.concatenate(flat[:6])).cuda()
+    a = pkg.StreamingTucker(s.dims, 1e-3, precision="fp64")
+    b = pkg.StreamingTucker(s.dims, 1e-3, precision="fp64")
+    a.init(x0, 6)
+    b.init(x0, 6)
+    for t in range(6, 20):
+        y = torch.from_numpy(flat[t]).cuda()
+        a.update(y)
+        b.update_block(y, 1)
+        assert a.ranks == b.ranks
+    np.testing.assert_array_equal(np.asarray(a.sv()), np.asarray(b.sv()))
+    f = pkg.StreamingTucker(s.dims, 1e-3, core_update="factored")
+    f.init(x0, 6)
+    with pytest.raises(StError) as ei:
+        f.update_block(torch.from_numpy(np.concatenate(flat[6:9])).cuda(), 3)
+    assert ei.value.code == ST_EINVAL
+    assert f.ranks[-1] > 0
