@@ -414,6 +414,8 @@ def main():
                     help="skip the Reconstruct/Project forward and VJP timings")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the FP32 vs bf16x3 comparison on the 512x512x256 stream")
+    ap.add_argument("--no-block", action="store_true",
+                    help="skip the block-update leg (b slices per call)")
     ap.add_argument("--no-sine", action="store_true",
                     help="skip the sine-wave stream and batch run (100x100x5000)")
     ap.add_argument("--headline-only", action="store_true",
@@ -441,7 +443,7 @@ def main():
         raise SystemExit(str(exc))
     if args.headline_only:
         args.no_variants = args.no_cpu_baseline = args.no_large = True
-        args.no_sine = args.no_grad = True
+        args.no_sine = args.no_grad = args.no_block = True
 
     import numpy as np
     import torch
@@ -600,6 +602,44 @@ def main():
                     return info
 
                 guarded(f"{prec}_{core}", variant, result["variants"])
+    if not args.no_block:
+        log("block updates (b slices per call) over the timed window")
+
+        def block_leg():
+            out = dict(workload=f"same stream and window (slices {t_begin}..{t_end - 1}); "
+                                "blocks of b slices per st_update_block call, "
+                                f"{args.precision}, literal core")
+            for bsz in (4, 16):
+                st = pkg.StreamingTucker(stream.dims, w["tau"], precision=args.precision)
+                st.init(data[:n_init].reshape(-1), n_init)
+                t = n_init
+                while t < t_begin:
+                    b = min(bsz, t_begin - t)
+                    st.update_block(data[t:t + b].reshape(-1), b)
+                    t += b
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                while t < t_end:
+                    b = min(bsz, t_end - t)
+                    st.update_block(data[t:t + b].reshape(-1), b)
+                    t += b
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                err2 = nrm2 = 0.0
+                for tt in range(n_slices):
+                    rec = st.reconstruct_slice(tt)
+                    err2 += torch.sum((rec.double() - data[tt].double()) ** 2).item()
+                    nrm2 += torch.sum(data[tt].double() ** 2).item()
+                out[f"b{bsz}"] = dict(value=round((t_end - t_begin) / dt, 3),
+                                      ms_per_block=round(1e3 * dt / ((t_end - t_begin) / bsz), 3),
+                                      ranks_final=list(st.ranks),
+                                      recon_error_bound=st.recon_error()[0],
+                                      true_rel_error=math.sqrt(err2 / nrm2),
+                                      qr_fixes=st.stats()["qr_total"])
+                st.close()
+            return out
+
+        guarded("block_updates", block_leg, result)
     del data
     torch.cuda.empty_cache()
     if not args.no_large:
