@@ -195,6 +195,13 @@ hipError_t launch_rot64(const FiberIn &in, const void *w, int w64, int64_t ldw, 
 // of all n rows does not fit LDS, the Gram is formed over pairs of 128-row
 // chunks and G must be given). `partials` holds gram_partial_elems doubles.
 enum class GramPrec : int { FP32 = 0, BF16X3 = 1, FP64 = 2 };
+// Mode-1 residual Gram of contiguous FP32 fibres (n <= 128, rows <= 64, FP32 or
+// bf16x3 Gram precision) from the exact FP64 projection P (F x rows, fibre-major,
+// ld rows) and U (FP64, n x rows, ld ldu): per-block partials as launch_gram's
+// (k_gramc.hip); reduce them with launch_gram_reduce.
+bool gram_contig_eligible(const FiberIn &in, int rows, GramPrec gp);
+hipError_t launch_gram_contig(const FiberIn &in, const double *U, int64_t ldu, int rows,
+                              const double *P, double *partials, int nblocks, hipStream_t s);
 int gram_blocks(int64_t F, int64_t n, GramPrec gp);
 size_t gram_partial_elems(int64_t n, int nblocks, GramPrec gp);
 hipError_t launch_gram(const FiberIn &in, const FiberW &w, int rows, double *partials,

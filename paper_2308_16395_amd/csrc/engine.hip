@@ -99,6 +99,18 @@ struct st_handle {
   double orth_tol = 1e-12;
   int64_t qr_total = 0;  // QR fixes applied since init
   int64_t blk = 1;       // slices in the update being processed (block updates)
+  int cus = 0;           // compute units of the device (cached)
+  int device_cus() {
+    if (cus <= 0) {
+      int c = 0;
+      cus = (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) ==
+                 hipSuccess &&
+             c > 0)
+                ? c
+                : 256;
+    }
+    return cus;
+  }
   double guard_rel = 0.0;
   int64_t max_rank_d = 0;
   hipStream_t stream = nullptr;
@@ -379,8 +391,10 @@ struct st_handle {
   // Gram of the residual (rows > 0) or of the tensor (rows == 0) for fibres of
   // length nk, then its eigendecomposition; eigenvalues (ascending) land in
   // hpin[0..nk), eigenvectors in G.
+  // P (optional): the FP64-product projection of the same fibres, which lets the
+  // mode-1 Gram of the slice form E from it (gram_contig) instead of projecting again
   int gram_eig(const FiberIn &in, const FiberW &w, int rows, int64_t nk, GramPrec pr,
-               bool e64) {
+               bool e64, const double *P = nullptr) {
     const int gnb = gram_blocks(in.F, nk, pr);
     hipError_t e = gram_part.ensure(gram_partial_elems(nk, gnb, pr));
     if (e == hipSuccess) e = G.ensure((size_t)nk * nk);
@@ -390,11 +404,22 @@ struct st_handle {
     if (e == hipSuccess) e = ensure_pinned(nk + 8);
     if (e != hipSuccess) return hipfail(e, "gram buffers");
     tic();
-    e = launch_gram(in, w, rows, gram_part.p, gnb, pr, e64, stream, G.p);
-    if (e != hipSuccess) return hipfail(e, "gram");
-    // recompute E (4 F n r) and form the lower triangle of E E^T (F n^2)
-    toc(ST_K_GRAM, 4.0 * in.F * nk * rows + 1.0 * in.F * nk * nk,
-        (in.x64 ? 8.0 : 4.0) * in.F * nk);
+    if (P != nullptr && e64 && w.w64 != nullptr && gram_contig_eligible(in, rows, pr)) {
+      // one block per CU (one wave per SIMD; each wave walks its fibre tiles)
+      const int nbc = std::min(gnb, device_cus());
+      e = launch_gram_contig(in, w.w64, nk, rows, P, gram_part.p, nbc, stream);
+      if (e == hipSuccess) e = launch_gram_reduce(gram_part.p, nbc, nk, G.p, stream);
+      if (e != hipSuccess) return hipfail(e, "gram");
+      // E = X - U P (2 F n r) and the lower triangle of E E^T (F n^2); X and P read
+      toc(ST_K_GRAM, 2.0 * in.F * nk * rows + 1.0 * in.F * nk * nk,
+          4.0 * in.F * nk + 8.0 * in.F * rows);
+    } else {
+      e = launch_gram(in, w, rows, gram_part.p, gnb, pr, e64, stream, G.p);
+      if (e != hipSuccess) return hipfail(e, "gram");
+      // recompute E (4 F n r) and form the lower triangle of E E^T (F n^2)
+      toc(ST_K_GRAM, 4.0 * in.F * nk * rows + 1.0 * in.F * nk * nk,
+          (in.x64 ? 8.0 : 4.0) * in.F * nk);
+    }
     tic();
     rocblas_status rs = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_lower,
                                          (rocblas_int)nk, G.p, (rocblas_int)nk, eigval.p,
@@ -827,7 +852,8 @@ int st_handle::do_update(const float *y, int64_t bsz) {
     // the FP64 Gram.
     const GramPrec gp = prec == Prec::FP64 ? GramPrec::FP64
                         : (prec == Prec::BF16X3 ? GramPrec::BF16X3 : GramPrec::FP32);
-    rc = gram_eig(in, wmat(k), (int)r[k], nk, gp, true);
+    // (Dout holds P_k from FP64 products: this loop runs with mp = FP64)
+    rc = gram_eig(in, wmat(k), (int)r[k], nk, gp, true, mp == Prec::FP64 ? Dout : nullptr);
     if (rc != ST_OK) return rc;
     int64_t rp;
     double tail;

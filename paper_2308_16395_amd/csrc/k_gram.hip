@@ -281,19 +281,40 @@ __global__ void gram_pair_reduce_kernel(const double *partials, int nblocks, int
   }
 }
 
-__global__ void gram_reduce_kernel(const double *partials, int nblocks, int ntiles, int64_t n,
-                                   double *G) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)ntiles * 256) return;
-  const int t = (int)(idx / 256), e = (int)(idx % 256);
-  int ti, tj;
-  tile_ij(t, ti, tj);
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partials[((size_t)b * ntiles + t) * 256 + e];
-  const int64_t i = 16 * ti + e / 16, j = 16 * tj + e % 16;
-  if (i < n && j < n) {
-    G[i + n * j] = s;
-    G[j + n * i] = s;
+// G from the per-block tile partials: a block takes 16 consecutive elements of
+// the tile sequence and 16 groups of partial blocks (thread (e, q) sums blocks
+// q, q + 16, ... with four interleaved accumulators, so its loads are in flight
+// together); the 16 group sums meet in LDS in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double *partials, int nblocks,
+                                                          int ntiles, int64_t n, double *G) {
+  __shared__ double red[16][17];
+  const int el = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int64_t idx = (int64_t)blockIdx.x * 16 + el;
+  const int64_t total = (int64_t)ntiles * 256;
+  const bool ok = idx < total;
+  const size_t stride = (size_t)ntiles * 256;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (ok) {
+    int b = q, u = 0;
+    for (; b + 48 < nblocks; b += 64) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] += partials[(size_t)(b + 16 * c) * stride + idx];
+    }
+    for (; b < nblocks; b += 16, u = (u + 1) & 3) a[u] += partials[(size_t)b * stride + idx];
+  }
+  red[q][el] = (a[0] + a[1]) + (a[2] + a[3]);
+  __syncthreads();
+  if (q == 0 && ok) {
+    double s = 0.0;
+    for (int g = 0; g < 16; ++g) s += red[g][el];
+    const int t = (int)(idx / 256), e = (int)(idx % 256);
+    int ti, tj;
+    tile_ij(t, ti, tj);
+    const int64_t i = 16 * ti + e / 16, j = 16 * tj + e % 16;
+    if (i < n && j < n) {
+      G[i + n * j] = s;
+      G[j + n * i] = s;
+    }
   }
 }
 
@@ -498,7 +519,7 @@ hipError_t launch_gram_reduce(const double *partials, int nblocks, int64_t n, do
   const int64_t jt = (n + 15) / 16;
   const int ntiles = (int)(jt * (jt + 1) / 2);
   const int64_t total = (int64_t)ntiles * 256;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 15) / 16)), dim3(256), 0, s,
                      partials, nblocks, ntiles, n, G);
   return hipGetLastError();
 }
