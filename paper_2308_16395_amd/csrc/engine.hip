@@ -149,6 +149,7 @@ struct st_handle {
   DBuf<double> Mf[2], Gf[2];  // M and G0 = V0^T V0 (r_d x r_d)
   DBuf<double> tvec, wvec, e1buf, tmp64, qrw, qrg, qvte;
   DBuf<double> bV, bE, bQ, bC, bsm;  // block updates: V at new rows, E, Q, FP64 core, small
+  DBuf<double> bsec;  // block updates: the middle-matrix SVD by row appends
   DBuf<int> qstat;
   DBuf<float> tmp32;
 
@@ -508,6 +509,7 @@ struct st_handle {
   int exact_coords(const float *y, const double **dout);
   int do_init(const float *x0, int64_t n_init);
   int do_update(const float *y, int64_t b = 1);
+  hipError_t block_rows_svd(const double *K, int n2, int rdi, int bi, int c, double tol, int nxt);
   int stream_block(const RowMap &map, const double *Dm, int64_t b, int64_t Rold, int64_t Rnew,
                    double eps, st_slice_stats &stt, const int64_t *rn, double delta2,
                    double ynorm2, double ms_modes, clk::time_point t0);
@@ -1564,6 +1566,45 @@ hipError_t st_handle::chunk_tn(const double *X, int64_t ldx, const double *Y, in
 // C~ = [C, Dm] U'' and U~_d = blockdiag(U_d, I_b) U''; commits like the
 // single-slice form.
 // ---------------------------------------------------------------------------
+// SVD of the block middle matrix K (rows 0..rd+b-1, columns 0..c-1 of the
+// n2 x n2 array, ld n2) as b row appends to [diag(S), 0]: each appended row,
+// rotated into the current right singular vectors (z = VK^T k_j), makes a
+// diagonal matrix plus one row whose SVD is the secular solve of the
+// single-slice update with no new column; VK and UK take its factors
+// (VK <- VK V'', UK <- [[UK, 0], [0, 1]] U''). The l zero columns of [diag(S), 0]
+// are poles at zero, deflated while their weights vanish. Writes U'' and V''
+// (ld n2) and S[nxt].
+hipError_t st_handle::block_rows_svd(const double *K, int n2, int rdi, int bi, int c, double tol,
+                                     int nxt) {
+  const int ldv = c + 1, ldu = c + bi;
+  const size_t nv = (size_t)ldv * c, nu = (size_t)ldu * c;
+  hipError_t e = bsec.ensure(4 * nv + 2 * nu + 3 * (size_t)c);
+  if (e == hipSuccess) e = ensure_secular(c + 1);
+  if (e != hipSuccess) return e;
+  double *VK[2] = {bsec.p, bsec.p + nv};
+  double *U2s = bsec.p + 2 * nv, *V2s = bsec.p + 3 * nv;
+  double *UK[2] = {bsec.p + 4 * nv, bsec.p + 4 * nv + nu};
+  double *sg[2] = {bsec.p + 4 * nv + 2 * nu, bsec.p + 4 * nv + 2 * nu + c};
+  double *z = sg[1] + c;
+  e = launch_block_rows_init(S[cur].p, rdi, c, VK[0], ldv, UK[0], ldu, sg[0], stream);
+  int k = 0;
+  for (int j = 0; j < bi && e == hipSuccess; ++j) {
+    e = launch_block_row_z(VK[k], ldv, c, K, n2, rdi + j, z, stream);
+    if (e == hipSuccess)
+      e = launch_secular_svd(secdata(c), sg[k], z, 0.0, nullptr, 0, tol, c, U2s, V2s, sg[k ^ 1],
+                             stream);
+    // VK (c x c) <- VK V''(0:c, :); UK ((c + j) x c) <- [UK U''(0:c, :); U''(c, :)]
+    if (e == hipSuccess) e = launch_ud_update(VK[k], ldv, c, c, V2s, c, VK[k ^ 1], ldv, stream);
+    if (e == hipSuccess)
+      e = launch_ud_update(UK[k], ldu, c + j, c, U2s, c, UK[k ^ 1], ldu, stream);
+    k ^= 1;
+  }
+  if (e == hipSuccess)
+    e = launch_block_rows_finish(VK[k], ldv, UK[k], ldu, sg[k], rdi, bi, c, V2.p, U2.p,
+                                 S[nxt].p, stream);
+  return e;
+}
+
 int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int64_t Rold,
                             int64_t Rnew, double eps, st_slice_stats &stt, const int64_t *rn,
                             double delta2, double ynorm2, double ms_modes,
@@ -1707,11 +1748,23 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
     if (e == hipSuccess) e = launch_pad_upper(G, c, n2, Rp, stream);
   } else if (e == hipSuccess) {
     e = hipMemsetAsync(qstat.p, 0, 2 * sizeof(int), stream);
-    if (e == hipSuccess) e = launch_pad_upper(nullptr, 0, n2, Rp, stream);
   }
-  if (e == hipSuccess) e = launch_jacobi_svd(K, n2, Wj, 60, qstat.p, stream);
-  if (e == hipSuccess) e = launch_jacobi_finish(K, Wj, Rp, n2, U2.p, V2.p, S[nxt].p, sig, stream);
-  toc(ST_K_SVD, 40.0 * (double)n2 * n2 * n2, 8.0 * 4.0 * nn2);
+  // K keeps its structure (diag(S) over b rows) unless the QR fix multiplied it
+  // by R^T: then, and for an empty old basis, the dense one-sided Jacobi SVD
+  const bool by_rows = !stt.qr_fired && rdi > 0;
+  if (by_rows) {
+    const double tol =
+        8.0 * 0x1p-53 * std::max(S_host.empty() ? 0.0 : S_host[0], std::sqrt(ynorm2));
+    if (e == hipSuccess) e = block_rows_svd(K, n2, rdi, bi, c, tol, nxt);
+    toc(ST_K_SVD, b * (60.0 * (double)c * c + 4.0 * (double)c * c * c + 2.0 * (double)c * c * b),
+        8.0 * b * (4.0 * (double)c * c + (double)c * (c + b)));
+  } else {
+    if (e == hipSuccess && !stt.qr_fired) e = launch_pad_upper(nullptr, 0, n2, Rp, stream);
+    if (e == hipSuccess) e = launch_jacobi_svd(K, n2, Wj, 60, qstat.p, stream);
+    if (e == hipSuccess)
+      e = launch_jacobi_finish(K, Wj, Rp, n2, U2.p, V2.p, S[nxt].p, sig, stream);
+    toc(ST_K_SVD, 40.0 * (double)n2 * n2 * n2, 8.0 * 4.0 * nn2);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(st2, qstat.p, sizeof(st2), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hipfail(e, "block middle matrix");

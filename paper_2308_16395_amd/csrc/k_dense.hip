@@ -354,6 +354,78 @@ hipError_t launch_ud_update_block(const double *Ud, int64_t ldo, int64_t nd, int
   return hipGetLastError();
 }
 
+// SVD of the block middle matrix by row appends. [diag(S), 0] (rd x c,
+// c = rd + l), padded with l zero rows, has the SVD I_c diag(S, 0) I_c^T; each
+// new row of K is then appended by the secular-equation SVD of a diagonal
+// matrix plus one row. Start: VK = I_c (ld ldv), UK(0:c, :) = I_c (ld ldu),
+// sig = [S, 0].
+__global__ void block_rows_init_kernel(const double *S, int rd, int c, double *VK, int ldv,
+                                       double *UK, int ldu, double *sig) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  const int i = idx % c, j = idx / c;
+  const double v = (i == j) ? 1.0 : 0.0;
+  VK[i + (size_t)ldv * j] = v;
+  UK[i + (size_t)ldu * j] = v;
+  if (j == 0) sig[i] = (i < rd) ? S[i] : 0.0;
+}
+
+hipError_t launch_block_rows_init(const double *S, int rd, int c, double *VK, int ldv, double *UK,
+                                  int ldu, double *sig, hipStream_t s) {
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_rows_init_kernel, dim3((unsigned)((c * c + 255) / 256)), dim3(256), 0,
+                     s, S, rd, c, VK, ldv, UK, ldu, sig);
+  return hipGetLastError();
+}
+
+// z = VK^T k for k = row `row` of K (ld n) over its first c columns: the new
+// row in the coordinates of the current right singular vectors. One wave per
+// entry of z (a column of VK, read contiguously), summed in a fixed order.
+__global__ __launch_bounds__(256) void block_row_z_kernel(const double *VK, int ldv, int c,
+                                                          const double *K, int n, int row,
+                                                          double *z) {
+  const int t = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t >= c) return;
+  double a = 0.0;
+  for (int i = lane; i < c; i += 64) a += VK[i + (size_t)ldv * t] * K[row + (size_t)n * i];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if (lane == 0) z[t] = a;
+}
+
+hipError_t launch_block_row_z(const double *VK, int ldv, int c, const double *K, int n, int row,
+                              double *z, hipStream_t s) {
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_row_z_kernel, dim3((unsigned)((c + 3) / 4)), dim3(256), 0, s, VK, ldv,
+                     c, K, n, row, z);
+  return hipGetLastError();
+}
+
+// The finished factors in the layout of the dense path (ld n2 = rd + b):
+// V'' = VK (c x c), U'' rows 0..rd-1 from UK's first rows and rows rd..rd+b-1
+// from the appended rows c..c+b-1 (UK's rows rd..c-1 are the padding, zero up
+// to rounding: the appended block has rank l), S = sig.
+__global__ void block_rows_finish_kernel(const double *VK, int ldv, const double *UK, int ldu,
+                                         const double *sig, int rd, int b, int c, double *V2,
+                                         double *U2, double *Snew) {
+  const int n2 = rd + b;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n2 * c) return;
+  const int i = idx % n2, j = idx / n2;
+  if (i < c) V2[i + (size_t)n2 * j] = VK[i + (size_t)ldv * j];
+  U2[i + (size_t)n2 * j] = UK[(i < rd ? i : c + (i - rd)) + (size_t)ldu * j];
+  if (idx < c) Snew[idx] = sig[idx];
+}
+
+hipError_t launch_block_rows_finish(const double *VK, int ldv, const double *UK, int ldu,
+                                    const double *sig, int rd, int b, int c, double *V2,
+                                    double *U2, double *Snew, hipStream_t s) {
+  const int total = (rd + b) * c;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_rows_finish_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     s, VK, ldv, UK, ldu, sig, rd, b, c, V2, U2, Snew);
+  return hipGetLastError();
+}
+
 // dst (Rn x cols, FP64) = src (FP32, old row layout, ld ld_src) through the row map
 __global__ void remap_rows_f32_kernel(const float *src, int64_t ld_src, RowMap map, int64_t Rn,
                                       int cols, double *dst) {

@@ -123,6 +123,14 @@ hipError_t launch_ud_update_block(const double *Ud, int64_t ldo, int64_t nd, int
                                   hipStream_t s);
 hipError_t launch_remap_rows_f32(const float *src, int64_t ld_src, RowMap map, int64_t Rn, int cols,
                                  double *dst, hipStream_t s);
+// Block middle-matrix SVD by row appends (k_dense.hip): start, rotated row, finish.
+hipError_t launch_block_rows_init(const double *S, int rd, int c, double *VK, int ldv, double *UK,
+                                  int ldu, double *sig, hipStream_t s);
+hipError_t launch_block_row_z(const double *VK, int ldv, int c, const double *K, int n, int row,
+                              double *z, hipStream_t s);
+hipError_t launch_block_rows_finish(const double *VK, int ldv, const double *UK, int ldu,
+                                    const double *sig, int rd, int b, int c, double *V2,
+                                    double *U2, double *Snew, hipStream_t s);
 // out[i] = sum over b < nb of part[b * n + i], in a fixed order
 hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, hipStream_t s);
 // delta = a - b (n rows) and per-block pairs (sum b * delta, sum delta^2) in
