@@ -310,6 +310,20 @@ int st_ttm_noalloc(const float *x, int32_t nmodes, const int64_t *dims, int32_t 
 int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, const float *a,
             int64_t rows, double *g, int32_t gram_precision, void *stream);
 
+/* Stateless symmetric eigendecomposition of a small FP64 matrix, the step of
+ * Alg. 1 (TruncatedSVD) that follows the Gram: a is an n x n column-major
+ * device matrix of which only the lower triangle is read (not modified); w
+ * (device, n doubles) receives every eigenvalue in ascending order; q (device,
+ * n x k column-major, may be NULL when k == 0) receives orthonormal
+ * eigenvectors of the k largest, column c for eigenvalue w[n-1-c]. The
+ * library's own kernels (Householder tridiagonalisation, multisection of the
+ * Sturm count, inverse iteration), the ones the streaming update uses for its
+ * Grams of order <= 128. 1 <= n <= 128, 0 <= k <= n; the call allocates
+ * n^2 + 3n doubles of workspace and returns after the work is done.
+ * Errors: ST_EINVAL (also when the device cannot hold the matrix in one
+ * block's shared memory), ST_ENOMEM, ST_EHIP. */
+int st_symeig(const double *a, int64_t n, double *w, double *q, int64_t k, void *stream);
+
 /* ---- Differentiation of the Tucker model (stateless) ----
  *
  * Reconstruct: X^ = G x_1 U_1 ... x_d U_d; Project: G = X x_1 U_1^T ... x_d U_d^T

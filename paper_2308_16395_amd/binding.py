@@ -46,7 +46,8 @@ STATUS_NAMES = {
 EXPORTED = ["st_create", "st_init", "st_update", "st_update_block", "st_ranks", "st_core",
             "st_factor", "st_sv", "st_recon_error", "st_stats", "st_reconstruct_slice",
             "st_destroy", "st_last_error", "st_ttm", "st_gram", "st_profile", "st_aux_v",
-            "st_tucker_workspace", "st_tucker_fwd", "st_tucker_bwd", "st_ttm_noalloc"]
+            "st_tucker_workspace", "st_tucker_fwd", "st_tucker_bwd", "st_ttm_noalloc",
+            "st_symeig"]
 ST_RECONSTRUCT, ST_PROJECT = 0, 1
 
 KERNEL_GROUPS = ["ttm1", "ttm", "gram", "eig", "ttm_ext", "isvd", "svd", "rot_v", "rot_c",
@@ -143,6 +144,8 @@ _sig = {
                                  C.c_int32, C.c_void_p]),
     "st_gram": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_int32, C.c_void_p,
                           C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    "st_symeig": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                            C.c_void_p]),
     "st_profile": (C.c_int, [_h, C.POINTER(st_kernel_profile), C.c_int32, C.c_int32]),
     "st_tucker_workspace": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.c_int32, C.POINTER(C.c_int64)]),
@@ -176,6 +179,7 @@ st_reconstruct_slice = lib.st_reconstruct_slice
 st_ttm = lib.st_ttm
 st_ttm_noalloc = lib.st_ttm_noalloc
 st_gram = lib.st_gram
+st_symeig = lib.st_symeig
 st_profile = lib.st_profile
 st_tucker_workspace = lib.st_tucker_workspace
 st_tucker_fwd = lib.st_tucker_fwd
@@ -254,6 +258,24 @@ def gram(x, dims, mode, a=None, precision="fp64", stream=None):
     if rc != ST_OK:
         raise StError(rc, "st_gram failed")
     return g.reshape(n, n, order="F")
+
+
+def symeig(a, k=0, stream=None):
+    """Eigenvalues (ascending) of the symmetric float64 CUDA matrix a (n x n,
+    lower triangle read, n <= 128) and orthonormal eigenvectors of the k
+    largest (column c for the c-th largest), through st_symeig."""
+    import torch
+
+    n = int(a.shape[0])
+    a = a.to(torch.float64).t().contiguous()  # column-major as the library reads it
+    w = torch.empty(n, dtype=torch.float64, device=a.device)
+    q = torch.empty((int(k), n), dtype=torch.float64, device=a.device)  # rows = columns of Q
+    _ready()
+    rc = st_symeig(C.c_void_p(a.data_ptr()), n, C.c_void_p(w.data_ptr()),
+                   C.c_void_p(q.data_ptr() if k > 0 else 0), int(k), _stream_arg(stream))
+    if rc != ST_OK:
+        raise StError(rc, "st_symeig failed")
+    return w, q.t()
 
 
 class StreamingTucker:

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstucker.so")
 SOURCES = ["k_fiber_ff.hip", "k_fiber_fd.hip", "k_fiber_dd.hip", "k_gram.hip", "k_rot.hip",
-           "k_isvd.hip", "k_ttm.hip", "k_gramc.hip", "k_dense.hip", "engine.hip", "tucker_ops.hip"]
+           "k_isvd.hip", "k_ttm.hip", "k_gramc.hip", "k_dense.hip", "k_eig.hip", "engine.hip", "tucker_ops.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 

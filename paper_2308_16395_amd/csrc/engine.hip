@@ -160,6 +160,8 @@ struct st_handle {
   DBuf<double> part, sums;
   DBuf<double> gram_part;
   DBuf<double> G, eigval, eigwork, Wnew, coef;
+  DBuf<double> eigtri;  // tridiagonal form and reflections of the last small Gram
+  bool eig_lazy = false;  // its eigenvectors are computed on demand (eig_top)
   DBuf<int> info;
   DBuf<double> colpart, q2part, p1, p2, p;
   DBuf<double> U2, V2;
@@ -422,15 +424,26 @@ struct st_handle {
           (in.x64 ? 8.0 : 4.0) * in.F * nk);
     }
     tic();
-    rocblas_status rs = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_lower,
-                                         (rocblas_int)nk, G.p, (rocblas_int)nk, eigval.p,
-                                         eigwork.p, info.p);
-    toc(ST_K_EIG, 9.0 * nk * nk * nk, 16.0 * nk * nk);
-    if (rs != rocblas_status_success) return fail(ST_ESOLVER, "rocsolver_dsyevd status %d", rs);
-    e = hipMemcpyAsync(hpin, eigval.p, nk * sizeof(double), hipMemcpyDeviceToHost, stream);
     int hinfo = 0;
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, stream);
+    eig_lazy = eig_small_supported((int)nk);
+    if (eig_lazy) {
+      // own kernels: eigenvalues now, eigenvectors of the kept ones in eig_top
+      e = eigtri.ensure(eig_work_elems((int)nk));
+      if (e == hipSuccess) e = launch_eig_tridiag(G.p, (int)nk, eigtri.p, stream);
+      if (e == hipSuccess) e = launch_eig_values(eigtri.p, (int)nk, eigval.p, stream);
+      toc(ST_K_EIG, (4.0 / 3.0) * nk * nk * nk + 10.0 * 64.0 * 3.0 * nk * nk, 8.0 * nk * nk);
+      if (e != hipSuccess) return hipfail(e, "eigenvalues");
+      e = hipMemcpyAsync(hpin, eigval.p, nk * sizeof(double), hipMemcpyDeviceToHost, stream);
+    } else {
+      rocblas_status rs = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_lower,
+                                           (rocblas_int)nk, G.p, (rocblas_int)nk, eigval.p,
+                                           eigwork.p, info.p);
+      toc(ST_K_EIG, 9.0 * nk * nk * nk, 16.0 * nk * nk);
+      if (rs != rocblas_status_success) return fail(ST_ESOLVER, "rocsolver_dsyevd status %d", rs);
+      e = hipMemcpyAsync(hpin, eigval.p, nk * sizeof(double), hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "eigenvalues");
     settle();
@@ -440,7 +453,22 @@ struct st_handle {
     return ST_OK;
   }
 
+  // Eigenvectors of the cnt largest eigenvalues of the last gram_eig into the
+  // last cnt columns of G (column nk-1-c for the c-th largest), where the
+  // library solver has not already written every eigenvector there.
+  int eig_top(int64_t nk, int64_t cnt) {
+    if (!eig_lazy || cnt <= 0) return ST_OK;
+    tic();
+    const hipError_t e =
+        launch_eig_vectors(eigtri.p, (int)nk, eigval.p, (int)cnt, G.p, nk, 0, stream);
+    toc(ST_K_EIG, 4.0 * cnt * nk * nk + 40.0 * cnt * nk, 8.0 * cnt * nk * 2.0);
+    if (e != hipSuccess) return hipfail(e, "eigenvectors");
+    return ST_OK;
+  }
+
   int append_columns(int k, int64_t c0, int64_t cnt) {
+    const int rc = eig_top(n[k], cnt);
+    if (rc != ST_OK) return rc;
     const int64_t nk = n[k];
     hipError_t e = Wnew.ensure((size_t)nk * cnt);
     if (e == hipSuccess) e = coef.ensure((size_t)std::max<int64_t>(c0, 1) * cnt);
@@ -627,6 +655,8 @@ int st_handle::do_init(const float *x0, int64_t n_init) {
         break;
       }
       ud_ld[cur] = ldu;
+      rc = eig_top(nk, rk);
+      if (rc != ST_OK) break;
       e = launch_new_columns(G.p, nk, nullptr, 0, (int)rk, Wnew.p, nullptr, stream);
       if (e == hipSuccess)
         e = hipMemcpy2DAsync(Ud[cur].p, ldu * sizeof(double), Wnew.p, nk * sizeof(double),
@@ -1956,6 +1986,7 @@ void st_handle::destroy() {
   gram_part.release();
   G.release();
   eigval.release();
+  eigtri.release();
   eigwork.release();
   Wnew.release();
   coef.release();
@@ -2450,6 +2481,23 @@ int st_gram(const float *x, int32_t nmodes, const int64_t *dims, int32_t mode, c
   if (part) (void)hipFree(part);
   if (G) (void)hipFree(G);
   if (a64) (void)hipFree(a64);
+  if (e == hipErrorOutOfMemory) return ST_ENOMEM;
+  return e == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_symeig(const double *a, int64_t n, double *w, double *q, int64_t k, void *stream) {
+  if (!a || !w || n < 1 || n > kEigMaxN || k < 0 || k > n || (k > 0 && !q)) return ST_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ST_EHIP;  // initialises the runtime
+  if (!eig_small_supported((int)n)) return ST_EINVAL;
+  double *work = nullptr;
+  hipError_t e = hipMalloc((void **)&work, eig_work_elems((int)n) * sizeof(double));
+  if (e == hipSuccess) e = launch_eig_tridiag(a, (int)n, work, s);
+  if (e == hipSuccess) e = launch_eig_values(work, (int)n, w, s);
+  if (e == hipSuccess) e = launch_eig_vectors(work, (int)n, w, (int)k, q, n, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (work) (void)hipFree(work);
   if (e == hipErrorOutOfMemory) return ST_ENOMEM;
   return e == hipSuccess ? ST_OK : ST_EHIP;
 }

@@ -123,6 +123,18 @@ hipError_t launch_ud_update_block(const double *Ud, int64_t ldo, int64_t nd, int
                                   hipStream_t s);
 hipError_t launch_remap_rows_f32(const float *src, int64_t ld_src, RowMap map, int64_t Rn, int cols,
                                  double *dst, hipStream_t s);
+// Symmetric eigendecomposition of small FP64 matrices (k_eig.hip), n <= kEigMaxN:
+// tridiagonalise A (lower triangle read) into work (eig_work_elems(n) doubles),
+// all eigenvalues ascending into w, then the eigenvectors of the k largest:
+// vector c (eigenvalue w[n-1-c]) into column c of Q (desc_cols) or column n-1-c.
+// eig_small_supported(n): n in range and its LDS fits the device.
+constexpr int kEigMaxN = 128;
+size_t eig_work_elems(int n);
+bool eig_small_supported(int n);
+hipError_t launch_eig_tridiag(const double *A, int n, double *work, hipStream_t s);
+hipError_t launch_eig_values(const double *work, int n, double *w, hipStream_t s);
+hipError_t launch_eig_vectors(const double *work, int n, const double *w, int k, double *Q,
+                              int64_t ldq, int desc_cols, hipStream_t s);
 // Block middle-matrix SVD by row appends (k_dense.hip): start, rotated row, finish.
 hipError_t launch_block_rows_init(const double *S, int rd, int c, double *VK, int ldv, double *UK,
                                   int ldu, double *sig, hipStream_t s);
