@@ -3,7 +3,7 @@
 // eigenvectors only for the k largest, the ones the rank rule keeps.
 //
 //   1. Householder tridiagonalisation in one block with the whole matrix in
-//      LDS. Step j reflects column j below the diagonal onto its first entry
+//      registers. Step j reflects column j below the diagonal onto its first entry
 //      (H_j = I - beta v v^T, the sign chosen against cancellation) and updates
 //      the trailing block as B <- B - v w^T - w v^T with p = beta B v and
 //      w = p - (beta / 2)(p^T v) v. The vectors v and the beta are kept.
@@ -12,9 +12,10 @@
 //      pivots of the LDL^T factorisation of T - x I, which is the number of
 //      eigenvalues below x) at one of 64 points of the current interval, so
 //      each step shrinks it 65-fold; tiny pivots are replaced by -pivmin.
-//   3. For each kept eigenvalue, inverse iteration on T: three solves with
-//      T - lambda I factored by Gaussian elimination with partial pivoting (a
-//      zero or tiny last pivot replaced by u ||T||), each iterate
+//   3. For each kept eigenvalue, inverse iteration on T in one wave (vectors
+//      spread over the lanes, the recurrences stepping across them): three
+//      solves with T - lambda I factored by Gaussian elimination with partial
+//      pivoting (a zero or tiny last pivot replaced by u ||T||), each iterate
 //      orthogonalised twice against the vectors already found in its cluster
 //      (eigenvalues closer than 1e-3 ||T||), equal eigenvalues shifted apart by
 //      ten ulps of ||T||. The reflections are then applied back,
@@ -34,19 +35,76 @@ namespace {
 
 constexpr double kU = 0x1p-53;
 
-// LDS of the tridiagonalisation: the matrix, 8 x 128 partial sums of B v, p, v
-size_t tridiag_lds_bytes(int n) { return ((size_t)n * n + 8 * 128 + 2 * 128) * sizeof(double); }
+// The value v holds in lane l (l the same in every lane).
+__device__ inline double lane_value(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
-__device__ inline double block_max(double v, double *scratch) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  v = wave_max(v);
+// v of the lane chosen by the DPP control CTRL (within rows of 16 lanes).
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum (max) over the 64 lanes of a wave with every lane active, the same value
+// in every lane and a fixed order: lane swaps within quads, then the mirror
+// within half rows and rows (DPP, no LDS), then the four row results.
+__device__ inline double wsum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+__device__ inline double wmax(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x140>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+}
+
+__device__ inline double wmin(double v) { return -wmax(-v); }
+
+// Block-wide sum / max (every thread active), the result in every thread;
+// scratch holds one double per wave.
+__device__ inline double bsum(double v, double *scratch) {
+  const int nw = (int)(blockDim.x >> 6);
+  v = wsum(v);
   __syncthreads();
-  if (lane == 0) scratch[wid] = v;
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = scratch[0];
+  for (int w = 1; w < nw; ++w) t += scratch[w];
+  return t;
+}
+
+__device__ inline double bmax(double v, double *scratch) {
+  const int nw = (int)(blockDim.x >> 6);
+  v = wmax(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
   __syncthreads();
   double t = scratch[0];
   for (int w = 1; w < nw; ++w) t = fmax(t, scratch[w]);
   return t;
+}
+
+// 1 / q: the hardware reciprocal refined by two Newton steps (about 1 ulp).
+__device__ inline double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
 }
 
 // Start vector of inverse iteration: a multiplicative hash of (row, vector)
@@ -61,134 +119,162 @@ __device__ inline double start_value(int i, int c) {
 
 // work = [Vh (n x n, column j holds v of step j in rows j+1..n-1), beta (n),
 //         d (n), e (n)]; A is read from its lower triangle.
-__global__ __launch_bounds__(1024) void eig_tridiag_kernel(const double *__restrict__ A, int n,
-                                                          double *__restrict__ work) {
-  extern __shared__ double lds[];
-  double *a = lds;              // n x n, ld n
-  double *pp = a + n * n;       // partial sums of B v: 8 x 128
-  double *pb = pp + 8 * 128;    // p = beta B v
-  double *vb = pb + 128;        // v
+// The matrix stays in registers: thread (row = tid % 128, part = tid / 128)
+// holds A(row, part + PARTS s), s < 128 / PARTS, PARTS = NTH / 128. The column
+// being reduced, v and p pass through LDS; the reflections, d, e and beta are
+// collected in LDS and written out once at the end.
+template <int NTH>
+__global__ __launch_bounds__(NTH) void eig_tridiag_kernel(const double *__restrict__ A, int n,
+                                                         double *__restrict__ work) {
+  constexpr int PARTS = NTH / 128, NS = 128 / PARTS;
+  __shared__ double xb[128], vb[128], pb[128], pp[PARTS * 128], tb[3 * 128];
+  extern __shared__ double vhs[];  // n x n
+  double *bts = tb, *dds = tb + 128, *ees = tb + 256;
   const int tid = threadIdx.x, lane = tid & 63;
-  double *Vh = work, *beta = work + (size_t)n * n, *dd = beta + n, *ee = dd + n;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int i = idx % n, k = idx / n;
-    a[idx] = (i >= k) ? A[i + (size_t)n * k] : A[k + (size_t)n * i];
+  const int row = tid & 127, part = tid >> 7;
+  double ar[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = part + PARTS * s;
+    ar[s] = (row < n && c < n) ? (row >= c ? A[row + (size_t)n * c] : A[c + (size_t)n * row])
+                               : 0.0;
   }
+  if (part == 0) xb[row] = ar[0];  // column 0 (zero past n)
   __syncthreads();
-  const int row = tid & 127, part = tid >> 7;  // 8 threads per row of the trailing block
   for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;
-    const double *x = a + (j + 1) + (size_t)n * j;  // column j below the diagonal
-    // sigma = sum_{i >= 1} x_i^2, formed alike in every wave
-    double s = 0.0;
-    for (int i = 1 + lane; i < m; i += 64) s += x[i] * x[i];
-    s = wave_sum(s);
-    const double x0 = x[0];
-    if (tid == 0) dd[j] = a[j + (size_t)n * j];
-    if (s == 0.0) {  // already reduced: H_j = I (every thread takes this branch)
+    const int jn = j + 1;
+    // sigma = sum_{i >= j+2} A(i, j)^2, formed alike in every wave
+    double s2 = 0.0;
+    for (int i = j + 2 + lane; i < n; i += 64) s2 += xb[i] * xb[i];
+    s2 = wsum(s2);
+    const double x0 = xb[jn];
+    if (tid == 0) dds[j] = xb[j];
+    if (s2 == 0.0) {  // already reduced: H_j = I (every thread takes this branch)
       if (tid == 0) {
-        ee[j] = x0;
-        beta[j] = 0.0;
+        ees[j] = x0;
+        bts[j] = 0.0;
       }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (part + PARTS * s == jn) xb[row] = ar[s];  // the next column
+      __syncthreads();
       continue;
     }
-    const double alpha = -copysign(sqrt(x0 * x0 + s), x0);
+    const double alpha = -copysign(sqrt(x0 * x0 + s2), x0);
     const double v0 = x0 - alpha;
-    const double bt = 2.0 / (v0 * v0 + s);
-    if (row < m) {
-      const double *brow = a + (j + 1 + row);
-      double acc = 0.0;
-      for (int kk = part; kk < m; kk += 8) {
-        const double vk = (kk == 0) ? v0 : x[kk];
-        acc += brow[(size_t)n * (j + 1 + kk)] * vk;
+    const double bt = 2.0 / (v0 * v0 + s2);
+    // partial sums of A v over this thread's columns; columns up to j (where v
+    // vanishes) and past n are skipped, and so are waves whose rows all lie
+    // outside the trailing block (both tests are uniform per wave)
+    const bool live = (row | 63) > j && (row & ~63) < n;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (live) {
+#pragma unroll
+      for (int s = 0; s < NS; s += 2) {
+        const int c = part + PARTS * s, c1 = c + PARTS;
+        if (c > j && c < n) acc0 = fma(ar[s], (c > jn) ? xb[c] : v0, acc0);
+        if (c1 > j && c1 < n) acc1 = fma(ar[s + 1], (c1 > jn) ? xb[c1] : v0, acc1);
       }
-      pp[part * 128 + row] = acc;
     }
+    pp[part * 128 + row] = acc0 + acc1;
     __syncthreads();
-    if (tid < m) {
-      double p = 0.0;
-      for (int q = 0; q < 8; ++q) p += pp[q * 128 + tid];
-      pb[tid] = bt * p;
-      const double vi = (tid == 0) ? v0 : x[tid];
+    if (tid < 128) {
+      double p = 0.0, vi = 0.0;
+      if (tid > j && tid < n) {
+#pragma unroll
+        for (int q = 0; q < PARTS; ++q) p += pp[q * 128 + tid];
+        p *= bt;
+        vi = (tid == jn) ? v0 : xb[tid];
+        vhs[tid + n * j] = vi;
+      }
+      pb[tid] = p;
       vb[tid] = vi;
-      Vh[(j + 1 + tid) + (size_t)n * j] = vi;
     }
     if (tid == 0) {
-      ee[j] = alpha;
-      beta[j] = bt;
+      ees[j] = alpha;
+      bts[j] = bt;
     }
     __syncthreads();
-    // K = (beta / 2) p^T v, formed alike in every wave; w = p - K v
-    double kv = 0.0;
-    for (int i = lane; i < m; i += 64) kv += pb[i] * vb[i];
-    const double K = 0.5 * bt * wave_sum(kv);
-    if (row < m) {
-      const double vi = vb[row], wi = pb[row] - K * vi;
-      double *brow = a + (j + 1 + row);
-      for (int kk = part; kk < m; kk += 8) {
-        const double vk = vb[kk], wk = pb[kk] - K * vk;
-        brow[(size_t)n * (j + 1 + kk)] -= vi * wk + wi * vk;
+    // K = (beta / 2) p^T v, formed alike in every wave; w = p - K v; A -= v w^T + w v^T
+    const double K = 0.5 * bt * wsum(pb[lane] * vb[lane] + pb[lane + 64] * vb[lane + 64]);
+    const double vr = vb[row], wr = pb[row] - K * vr;
+    if (live) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int c = part + PARTS * s;
+        if (c > j && c < n) {  // v and w vanish elsewhere
+          const double vc = vb[c], wc = pb[c] - K * vc;
+          ar[s] -= vr * wc + wr * vc;
+          if (c == jn) xb[row] = ar[s];  // the next column, updated
+        }
       }
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    if (n >= 2) {
-      dd[n - 2] = a[(n - 2) + (size_t)n * (n - 2)];
-      ee[n - 2] = a[(n - 1) + (size_t)n * (n - 2)];
-      beta[n - 2] = 0.0;
+  if (n >= 2 && tid == 0) {
+    dds[n - 2] = xb[n - 2];
+    ees[n - 2] = xb[n - 1];
+    bts[n - 2] = 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (row == n - 1 && part + PARTS * s == n - 1) {
+      dds[n - 1] = ar[s];
+      bts[n - 1] = 0.0;
     }
-    dd[n - 1] = a[(n - 1) + (size_t)n * (n - 1)];
-    beta[n - 1] = 0.0;
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += NTH) work[idx] = vhs[idx];
+  double *beta = work + (size_t)n * n;
+  for (int i = tid; i < n; i += NTH) {
+    beta[i] = bts[i];
+    beta[n + i] = dds[i];
+    beta[2 * n + i] = (i + 1 < n) ? ees[i] : 0.0;
   }
 }
 
 // w[i] (ascending) = the i-th eigenvalue of T; one wave per eigenvalue.
 __global__ __launch_bounds__(256) void eig_values_kernel(const double *__restrict__ work, int n,
                                                         double *__restrict__ w) {
-  __shared__ double sd[kEigMaxN], se2[kEigMaxN], bnd[3];
+  __shared__ double sd[kEigMaxN], se2[kEigMaxN];
   const int tid = threadIdx.x, lane = tid & 63;
   const double *dd = work + (size_t)n * n + n, *ee = dd + n;
-  for (int i = tid; i < n; i += blockDim.x) {
-    sd[i] = dd[i];
-    se2[i] = (i + 1 < n) ? ee[i] * ee[i] : 0.0;
-  }
-  if (tid == 0) {
-    // Gershgorin interval, widened by a few ulps, and the pivot floor
-    double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
-      lo = fmin(lo, dd[i] - r);
-      hi = fmax(hi, dd[i] + r);
-      if (i + 1 < n) emax2 = fmax(emax2, ee[i] * ee[i]);
-    }
-    const double pivmin = DBL_MIN * fmax(1.0, emax2);
-    const double tn = fmax(fabs(lo), fabs(hi));
-    bnd[0] = lo - (4.0 * kU * tn + pivmin);
-    bnd[1] = hi + (4.0 * kU * tn + pivmin);
-    bnd[2] = pivmin;
+  for (int r = tid; r < n; r += blockDim.x) {
+    sd[r] = dd[r];
+    se2[r] = (r + 1 < n) ? ee[r] * ee[r] : 0.0;
   }
   __syncthreads();
   const int i = blockIdx.x * 4 + (tid >> 6);
-  if (i >= n) return;
-  double lo = bnd[0], hi = bnd[1];
-  const double pivmin = bnd[2];
+  if (i >= n) return;  // the whole wave
+  // Gershgorin interval, widened by a few ulps, and the pivot floor
+  double lo_l = INFINITY, hi_l = -INFINITY, em2 = 0.0;
+  for (int r = lane; r < n; r += 64) {
+    const double rad = (r >= 1 ? fabs(ee[r - 1]) : 0.0) + (r + 1 < n ? fabs(ee[r]) : 0.0);
+    lo_l = fmin(lo_l, sd[r] - rad);
+    hi_l = fmax(hi_l, sd[r] + rad);
+    em2 = fmax(em2, se2[r]);
+  }
+  const double pivmin = DBL_MIN * fmax(1.0, wmax(em2));
+  const double glo = wmin(lo_l), ghi = wmax(hi_l);
+  const double tn = fmax(fabs(glo), fabs(ghi));
+  double lo = glo - (4.0 * kU * tn + pivmin), hi = ghi + (4.0 * kU * tn + pivmin);
   for (int it = 0; it < 16; ++it) {
     const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
     double q = sd[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
+    q = (fabs(q) < pivmin) ? -pivmin : q;
     int cnt = q < 0.0 ? 1 : 0;
+#pragma unroll 4
     for (int kk = 1; kk < n; ++kk) {
-      q = (sd[kk] - x) - se2[kk - 1] / q;
-      if (fabs(q) < pivmin) q = -pivmin;
+      q = fma(-se2[kk - 1], recip(q), sd[kk] - x);
+      q = (fabs(q) < pivmin) ? -pivmin : q;
       cnt += q < 0.0 ? 1 : 0;
     }
     // lambda_i >= x exactly where fewer than i + 1 eigenvalues lie below x: a
     // prefix of the (ascending) lanes
     const unsigned long long ok = __ballot(cnt <= i);
     const int l = (ok == ~0ull) ? 64 : __builtin_ctzll(~ok);
-    const double nlo = (l > 0) ? __shfl(x, l - 1, kWave) : lo;
-    const double nhi = (l < 64) ? __shfl(x, l, kWave) : hi;
+    const double nlo = (l > 0) ? lane_value(x, l - 1) : lo;
+    const double nhi = (l < 64) ? lane_value(x, l) : hi;
     if (nlo == lo && nhi == hi) break;
     lo = nlo;
     hi = nhi;
@@ -197,22 +283,27 @@ __global__ __launch_bounds__(256) void eig_values_kernel(const double *__restric
 }
 
 // Eigenvectors of the k largest eigenvalues (w ascending): vector c (eigenvalue
-// w[n-1-c]) goes to column c of Q (desc_cols) or to column n-1-c.
+// w[n-1-c]) goes to column c of Q (desc_cols) or to column n-1-c. Thread 0 runs
+// the recurrences of inverse iteration on LDS arrays (their loads do not
+// depend on the running values, so they are issued ahead), the block the
+// vector operations; then the reflections, staged in LDS, are applied by every
+// wave.
 __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restrict__ work, int n,
                                                          const double *__restrict__ w, int k,
                                                          double *Q, int64_t ldq, int desc_cols) {
-  __shared__ double sd[kEigMaxN], se[kEigMaxN], u1[kEigMaxN], u2[kEigMaxN], u3[kEigMaxN],
-      lm[kEigMaxN], xs[kEigMaxN], coef[kEigMaxN], red[4];
-  __shared__ int piv[kEigMaxN];
+  __shared__ double sd[kEigMaxN], se[kEigMaxN], lm[kEigMaxN], ri[kEigMaxN], ua[kEigMaxN],
+      ub[kEigMaxN], pv[kEigMaxN], xs[kEigMaxN], coef[kEigMaxN], red[4];
+  extern __shared__ double vh[];  // n x n reflections
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const double *Vh = work, *beta = work + (size_t)n * n, *dd = beta + n, *ee = dd + n;
+  const double *beta = work + (size_t)n * n, *dd = beta + n, *ee = dd + n;
   auto colq = [&](int c) { return Q + ldq * (desc_cols ? c : n - 1 - c); };
+  for (int idx = tid; idx < n * n; idx += blockDim.x) vh[idx] = work[idx];
   for (int i = tid; i < n; i += blockDim.x) {
     sd[i] = dd[i];
     se[i] = (i + 1 < n) ? ee[i] : 0.0;
   }
-  const double tn = block_max(tid < n ? fabs(dd[tid]) : 0.0, red) +
-                    2.0 * block_max(tid + 1 < n ? fabs(ee[tid]) : 0.0, red);
+  const double tn = bmax(tid < n ? fabs(dd[tid]) : 0.0, red) +
+                    2.0 * bmax(tid + 1 < n ? fabs(ee[tid]) : 0.0, red);
   const double gap_tol = 1e-3 * tn, sep = 10.0 * kU * tn;
   const double tiny = fmax(kU * tn, DBL_MIN);
   int cs = 0;
@@ -221,57 +312,55 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
     double lam = w[n - 1 - c];
     if (c > 0) {
       const double gap = w[n - c] - lam;
-      if (gap > gap_tol) cs = c;               // a new cluster starts
+      if (gap > gap_tol) cs = c;                  // a new cluster starts
       else if (gap <= sep) lam = lam_prev - sep;  // equal: shift apart
     }
     lam_prev = lam;
     if (tid == 0) {
-      // T - lam I = P L U, U with two superdiagonals (u2, u3)
-      double p = sd[0] - lam, q = (n > 1) ? se[0] : 0.0;
+      // T - lam I = P L U (U with two superdiagonals): multipliers lm, 1/u1 in
+      // ri, u2 in ua, u3 in ub, row swaps in pv
+      double p = sd[0] - lam, q = se[0];
       for (int kk = 0; kk + 1 < n; ++kk) {
-        const double dn = sd[kk + 1] - lam, en = (kk + 2 < n) ? se[kk + 1] : 0.0, ek = se[kk];
-        if (fabs(p) >= fabs(ek)) {
-          if (p == 0.0) p = tiny;
-          const double l = ek / p;
-          lm[kk] = l;
-          u1[kk] = p;
-          u2[kk] = q;
-          u3[kk] = 0.0;
-          piv[kk] = 0;
-          p = dn - l * q;
-          q = en;
-        } else {
-          const double l = p / ek;
-          lm[kk] = l;
-          u1[kk] = ek;
-          u2[kk] = dn;
-          u3[kk] = en;
-          piv[kk] = 1;
-          p = q - l * dn;
-          q = -l * en;
-        }
+        const double dn = sd[kk + 1] - lam, ek = se[kk], en = se[kk + 1];
+        const bool sw = fabs(p) < fabs(ek);
+        const double pz = (!sw && p == 0.0) ? tiny : p;
+        const double r1 = recip(sw ? ek : pz);
+        const double l = (sw ? pz : ek) * r1;
+        lm[kk] = l;
+        ri[kk] = r1;
+        ua[kk] = sw ? dn : q;
+        ub[kk] = sw ? en : 0.0;
+        pv[kk] = sw ? 1.0 : 0.0;
+        const double pn = sw ? fma(-l, dn, q) : fma(-l, q, dn);
+        q = sw ? -l * en : en;
+        p = pn;
       }
-      if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
-      u1[n - 1] = p;
+      p = (fabs(p) < tiny) ? ((p < 0.0) ? -tiny : tiny) : p;
+      ri[n - 1] = recip(p);
     }
     double xi = (tid < n) ? start_value(tid, c) : 0.0;
     for (int it = 0; it < 3; ++it) {
       if (tid < n) xs[tid] = xi;
       __syncthreads();
       if (tid == 0) {
+        // the row swaps and L, then U
+        double carry = xs[0];
+#pragma unroll 4
         for (int kk = 0; kk + 1 < n; ++kk) {
-          if (piv[kk]) {
-            const double t = xs[kk];
-            xs[kk] = xs[kk + 1];
-            xs[kk + 1] = t;
-          }
-          xs[kk + 1] -= lm[kk] * xs[kk];
+          const double nx = xs[kk + 1];
+          const bool sw = pv[kk] != 0.0;
+          const double a = sw ? nx : carry;
+          carry = fma(-lm[kk], a, sw ? carry : nx);
+          xs[kk] = a;
         }
-        xs[n - 1] /= u1[n - 1];
-        for (int kk = n - 2; kk >= 0; --kk) {
-          double s = xs[kk] - u2[kk] * xs[kk + 1];
-          if (kk + 2 < n) s -= u3[kk] * xs[kk + 2];
-          xs[kk] = s / u1[kk];
+        xs[n - 1] = carry;
+        double y1 = 0.0, y2 = 0.0;
+#pragma unroll 4
+        for (int kk = n - 1; kk >= 0; --kk) {
+          const double y = fma(-ub[kk], y2, fma(-ua[kk], y1, xs[kk])) * ri[kk];
+          xs[kk] = y;
+          y2 = y1;
+          y1 = y;
         }
       }
       __syncthreads();
@@ -280,10 +369,10 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
       for (int rep = 0; rep < 2 && c > cs; ++rep) {
         for (int p = cs + wid; p < c; p += 4) {
           const double *zp = colq(p);
-          double s = 0.0;
-          for (int i = lane; i < n; i += 64) s += zp[i] * xs[i];
-          s = wave_sum(s);
-          if (lane == 0) coef[p - cs] = s;
+          double sp = 0.0;
+          for (int i = lane; i < n; i += 64) sp += zp[i] * xs[i];
+          sp = wsum(sp);
+          if (lane == 0) coef[p - cs] = sp;
         }
         __syncthreads();
         if (tid < n) {
@@ -295,9 +384,9 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
         if (tid < n) xs[tid] = yi;
         __syncthreads();
       }
-      const double mx = block_max(fabs(yi), red);
+      const double mx = bmax(fabs(yi), red);
       if (mx > 0.0) yi /= mx;
-      const double nr = block_sum(yi * yi, red);
+      const double nr = bsum(yi * yi, red);
       xi = nr > 0.0 ? yi / sqrt(nr) : 0.0;
     }
     if (tid < n) colq(c)[tid] = xi;
@@ -310,12 +399,12 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
     for (int j = n - 3; j >= 0; --j) {
       const double bj = beta[j];
       if (bj == 0.0) continue;
-      const double *v = Vh + (size_t)n * j;
+      const double *v = vh + (size_t)n * j;
       const double v0 = (lane > j && lane < n) ? v[lane] : 0.0;
       const double v1 = (lane + 64 > j && lane + 64 < n) ? v[lane + 64] : 0.0;
-      const double s = bj * wave_sum(v0 * z0 + v1 * z1);
-      z0 -= s * v0;
-      z1 -= s * v1;
+      const double sj = bj * wsum(v0 * z0 + v1 * z1);
+      z0 -= sj * v0;
+      z1 -= sj * v1;
     }
     if (lane < n) zc[lane] = z0;
     if (lane + 64 < n) zc[lane + 64] = z1;
@@ -325,6 +414,10 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
 }  // namespace
 
 size_t eig_work_elems(int n) { return (size_t)n * n + 3 * (size_t)n; }
+
+// dynamic LDS of the tridiagonalisation and of the vectors (the staged
+// reflections); each kernel adds at most 16 KiB of static LDS
+static size_t vectors_lds_bytes(int n) { return (size_t)n * n * sizeof(double); }
 
 bool eig_small_supported(int n) {
   if (n < 1 || n > kEigMaxN) return false;
@@ -336,17 +429,25 @@ bool eig_small_supported(int n) {
       v = 0;
     limit = v;
   }
-  return tridiag_lds_bytes(n) <= (size_t)limit;
+  return vectors_lds_bytes(n) + 16384 <= (size_t)limit;
+}
+
+template <int NTH>
+static hipError_t launch_tridiag_t(const double *A, int n, double *work, hipStream_t s) {
+  const size_t lds = (size_t)n * n * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void *)eig_tridiag_kernel<NTH>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eig_tridiag_kernel<NTH>), dim3(1), dim3(NTH), lds, s, A, n, work);
+  return hipGetLastError();
 }
 
 hipError_t launch_eig_tridiag(const double *A, int n, double *work, hipStream_t s) {
   if (n < 1 || n > kEigMaxN) return hipErrorInvalidValue;
-  const size_t lds = tridiag_lds_bytes(n);
-  hipError_t e = hipFuncSetAttribute((const void *)eig_tridiag_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(eig_tridiag_kernel, dim3(1), dim3(1024), lds, s, A, n, work);
-  return hipGetLastError();
+  // 16 waves: each step is a chain of short phases between barriers, and with
+  // fewer waves per SIMD their latencies are not covered (512 threads took
+  // 1.3x and 256 threads 2.5x as long at n = 128)
+  return launch_tridiag_t<1024>(A, n, work, s);
 }
 
 hipError_t launch_eig_values(const double *work, int n, double *w, hipStream_t s) {
@@ -360,7 +461,11 @@ hipError_t launch_eig_vectors(const double *work, int n, const double *w, int k,
                               int64_t ldq, int desc_cols, hipStream_t s) {
   if (n < 1 || n > kEigMaxN || k < 0 || k > n || ldq < n) return hipErrorInvalidValue;
   if (k == 0) return hipSuccess;
-  hipLaunchKernelGGL(eig_vectors_kernel, dim3(1), dim3(256), 0, s, work, n, w, k, Q, ldq,
+  const size_t lds = vectors_lds_bytes(n);
+  hipError_t e = hipFuncSetAttribute((const void *)eig_vectors_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(eig_vectors_kernel, dim3(1), dim3(256), lds, s, work, n, w, k, Q, ldq,
                      desc_cols);
   return hipGetLastError();
 }
