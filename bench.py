@@ -168,6 +168,36 @@ def large_bench(n_init=20, warmup=3, steps=30):
     return out
 
 
+def symeig_bench():
+    """The library's small symmetric eigensolver (st_symeig: the step of Alg. 1
+    after the Gram) at the Gram orders of the blob stream (16, 64, 128) keeping
+    k = 1, 2, 8 eigenvectors, on seeded Gram matrices X X^T (X: n x 4n, columns
+    scaled by a decaying spectrum) resident in HBM; wall time per call,
+    including its workspace allocation and the final synchronisation."""
+    import numpy as np
+    import torch
+
+    import paper_2308_16395_amd.binding as bd
+
+    out = dict(workload="st_symeig on seeded Gram matrices X X^T, X: n x 4n, column "
+                        "scales 10^(-4 j / 4n); wall ms per call")
+    rng = np.random.default_rng(2308)
+    for n in (16, 64, 128):
+        x = rng.standard_normal((n, 4 * n)) * np.logspace(0, -4, 4 * n)[None, :]
+        g = torch.from_numpy(x @ x.T).cuda()
+        for k in (1, 2, 8):
+            for _ in range(3):
+                bd.symeig(g, k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                bd.symeig(g, k)
+            torch.cuda.synchronize()
+            out[f"n{n}_k{k}"] = round((time.perf_counter() - t0) / 20 * 1e3, 3)
+    log(f"symeig: {out}")
+    return out
+
+
 def sine_bench():
     """The sine-wave experiment of Sec. 5.1 (100 x 100 x 5000, rank bump at slice
     2500, eta 1e-3, tau 1e-2): the streaming path (initial ST-HOSVD on 200
@@ -423,6 +453,9 @@ def main():
     ap.add_argument("--sine-only", action="store_true",
                     help="run only the sine-wave stream and batch run and print their "
                          "JSON (for profiling that workload alone)")
+    ap.add_argument("--symeig-only", action="store_true",
+                    help="run only the small symmetric eigensolver timings and print "
+                         "their JSON (for profiling its kernels alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size "
                          "kernel against which HBM byte counters are calibrated)")
@@ -434,6 +467,9 @@ def main():
         sys.exit(2)
     if args.sine_only:
         print(json.dumps(dict(sine_wave=sine_bench())), flush=True)
+        return
+    if args.symeig_only:
+        print(json.dumps(dict(symeig=symeig_bench())), flush=True)
         return
     w = WORKLOAD
     n_init, n_slices = w["n_init"], w["n_slices"]
@@ -651,6 +687,8 @@ def main():
     if not args.no_grad:
         log("timing Reconstruct/Project forward and VJPs")
         guarded("differentiation", grad_bench, result)
+    if not args.headline_only:
+        guarded("symeig", symeig_bench, result)
     print(json.dumps(result), flush=True)
 
 
