@@ -40,6 +40,44 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// The value v holds in lane l (l the same in every lane).
+__device__ inline double lane_value(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// v of the lane chosen by the DPP control CTRL (within rows of 16 lanes).
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum (max) over the 64 lanes of a wave with every lane active, the same value
+// in every lane and a fixed order: lane swaps within quads, then the mirror
+// within half rows and rows (DPP moves, no LDS), then the four row results.
+// Faster than wave_sum, whose cross-lane moves go through the LDS crossbar.
+__device__ inline double dpp_wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+__device__ inline double dpp_wave_max(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x140>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+}
+
 // Block-wide sum of one double per thread; result valid in every thread.
 // `scratch` must hold blockDim.x / 64 doubles.
 __device__ inline double block_sum(double v, double *scratch) {

@@ -107,7 +107,11 @@ hipError_t launch_arrow_rt(const double *S, const double *p, const double *ee, c
 // One-sided Jacobi on the columns of A (n x n): A <- A J, W <- J (W = I on
 // entry, set here). Sweeps run the round-robin ordering (every pair once per
 // sweep, n/2 disjoint pairs per round, one wavefront per pair) until a sweep
-// makes no rotation or max_sweeps is reached (status[0] = 2 then).
+// makes no rotation or max_sweeps is reached (status[0] = 2 then). A wave
+// holds its pair's two columns in registers (KR entries per lane, n <= 64 KR;
+// KR = 0: any n, columns re-read from memory), takes the three inner products
+// with DPP reductions and rotates from the registers.
+template <int KR>
 __global__ __launch_bounds__(1024) void jacobi_svd_kernel(double *A, int n, double *W,
                                                          int max_sweeps, int *status) {
   __shared__ int rotated;
@@ -134,31 +138,74 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(double *A, int n, doub
         const int i = a < b ? a : b, j = a < b ? b : a;
         double *ci = A + (size_t)n * i, *cj = A + (size_t)n * j;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int k = lane; k < n; k += 64) {
-          const double x = ci[k], y = cj[k];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        if constexpr (KR > 0) {
+          double x[KR], y[KR];
+#pragma unroll
+          for (int q = 0; q < KR; ++q) {
+            const int k = lane + 64 * q;
+            x[q] = k < n ? ci[k] : 0.0;
+            y[q] = k < n ? cj[k] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < KR; ++q) {
+            al = fma(x[q], x[q], al);
+            be = fma(y[q], y[q], be);
+            ga = fma(x[q], y[q], ga);
+          }
+          al = dpp_wave_sum(al);
+          be = dpp_wave_sum(be);
+          ga = dpp_wave_sum(ga);
+          if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+            double *wi = W + (size_t)n * i, *wj = W + (size_t)n * j;
+            double u[KR], v[KR];
+#pragma unroll
+            for (int q = 0; q < KR; ++q) {
+              const int k = lane + 64 * q;
+              u[q] = k < n ? wi[k] : 0.0;
+              v[q] = k < n ? wj[k] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < KR; ++q) {
+              const int k = lane + 64 * q;
+              if (k < n) {
+                ci[k] = c * x[q] - sn * y[q];
+                cj[k] = sn * x[q] + c * y[q];
+                wi[k] = c * u[q] - sn * v[q];
+                wj[k] = sn * u[q] + c * v[q];
+              }
+            }
+            if (lane == 0) rotated = 1;
+          }
+        } else {
           for (int k = lane; k < n; k += 64) {
             const double x = ci[k], y = cj[k];
-            ci[k] = c * x - sn * y;
-            cj[k] = sn * x + c * y;
+            al += x * x;
+            be += y * y;
+            ga += x * y;
           }
-          double *wi = W + (size_t)n * i, *wj = W + (size_t)n * j;
-          for (int k = lane; k < n; k += 64) {
-            const double x = wi[k], y = wj[k];
-            wi[k] = c * x - sn * y;
-            wj[k] = sn * x + c * y;
+          al = dpp_wave_sum(al);
+          be = dpp_wave_sum(be);
+          ga = dpp_wave_sum(ga);
+          if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+            for (int k = lane; k < n; k += 64) {
+              const double x = ci[k], y = cj[k];
+              ci[k] = c * x - sn * y;
+              cj[k] = sn * x + c * y;
+            }
+            double *wi = W + (size_t)n * i, *wj = W + (size_t)n * j;
+            for (int k = lane; k < n; k += 64) {
+              const double x = wi[k], y = wj[k];
+              wi[k] = c * x - sn * y;
+              wj[k] = sn * x + c * y;
+            }
+            if (lane == 0) rotated = 1;
           }
-          if (lane == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -171,7 +218,17 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(double *A, int n, doub
 
 hipError_t launch_jacobi_svd(double *A, int n, double *W, int max_sweeps, int *status,
                              hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, A, n, W, max_sweeps, status);
+  const int kr = (n + 63) / 64;
+  if (kr <= 1)
+    hipLaunchKernelGGL(jacobi_svd_kernel<1>, dim3(1), dim3(1024), 0, s, A, n, W, max_sweeps, status);
+  else if (kr == 2)
+    hipLaunchKernelGGL(jacobi_svd_kernel<2>, dim3(1), dim3(1024), 0, s, A, n, W, max_sweeps, status);
+  else if (kr == 3)
+    hipLaunchKernelGGL(jacobi_svd_kernel<3>, dim3(1), dim3(1024), 0, s, A, n, W, max_sweeps, status);
+  else if (kr == 4)
+    hipLaunchKernelGGL(jacobi_svd_kernel<4>, dim3(1), dim3(1024), 0, s, A, n, W, max_sweeps, status);
+  else
+    hipLaunchKernelGGL(jacobi_svd_kernel<0>, dim3(1), dim3(1024), 0, s, A, n, W, max_sweeps, status);
   return hipGetLastError();
 }
 
