@@ -129,3 +129,72 @@ def test_zero_row_is_identity(sec):
     u2, sn, v2, counts = _svd(sec, s, np.zeros(3), 0.0, False)
     np.testing.assert_allclose(sn, s, rtol=1e-15)
     np.testing.assert_allclose(np.abs(v2[:3, :]), np.eye(3), atol=1e-15)
+
+
+def _block_rows_svd(lib, S, P, X):
+    """The block middle-matrix SVD as the library forms it: b row appends to
+    [diag(S), 0] (c = rd + l columns, l zero poles), each a secular solve of a
+    diagonal matrix plus one row without a new column, with the same flat
+    buffer layouts as the kernels (V_K: ld c + 1, U_K: ld c + b; the padding
+    rows rd..c-1 of U_K dropped at the end)."""
+    rd, b = P.shape
+    ell = X.shape[1]
+    c = rd + ell
+    ldv, ldu = c + 1, c + b
+    vk = np.zeros(ldv * c)
+    uk = np.zeros(ldu * c)
+    for i in range(c):
+        vk[i + ldv * i] = 1.0
+        uk[i + ldu * i] = 1.0
+    sig = np.concatenate([S, np.zeros(ell)])
+    kmat = np.zeros((rd + b, c))
+    kmat[:rd, :rd] = np.diag(S)
+    kmat[rd:, :rd] = P.T
+    kmat[rd:, rd:] = X
+    for j in range(b):
+        vkm = vk.reshape((ldv, c), order="F")[:c, :]
+        z = vkm.T @ kmat[rd + j, :]
+        tol = 8 * 2.0 ** -53 * max(S[0], np.sqrt((P ** 2).sum() + (X ** 2).sum()))
+        u2 = np.zeros((c + 1) * c)
+        v2 = np.zeros((c + 1) * c)
+        sn = np.zeros(c + 1)
+        counts = np.zeros(3, dtype=np.int32)
+        nt = lib.sec_svd_host(c, np.ascontiguousarray(sig), np.ascontiguousarray(z), 0.0, 0, tol,
+                              u2, v2, sn, counts)
+        assert nt == c
+        u2m = u2.reshape((c + 1, c), order="F")
+        v2m = v2.reshape((c + 1, c), order="F")
+        vk = np.zeros(ldv * c)
+        vk.reshape((ldv, c), order="F")[:c, :] = vkm @ v2m[:c, :]
+        m = c + j  # rows of U_K so far
+        ukm = uk.reshape((ldu, c), order="F")
+        new = np.zeros((ldu, c))
+        new[:m, :] = ukm[:m, :] @ u2m[:c, :]
+        new[m, :] = u2m[c, :]
+        uk = new.ravel(order="F")
+        sig = sn[:c].copy()
+    ukm = uk.reshape((ldu, c), order="F")
+    u = np.vstack([ukm[:rd, :], ukm[c:c + b, :]])
+    pad = ukm[rd:c, :]
+    return u, sig, vk.reshape((ldv, c), order="F")[:c, :], kmat, pad
+
+
+@pytest.mark.parametrize("rd,b,ell", [(12, 4, 4), (40, 4, 2), (60, 16, 16), (110, 16, 3),
+                                      (30, 3, 0), (5, 1, 1)])
+def test_block_middle_matrix_by_row_appends(sec, rd, b, ell):
+    """The block update's middle matrix [[diag S, 0], [P^T, X]] by b secular
+    row appends equals its SVD (numpy), with the l zero poles deflating and the
+    padding rows of U vanishing."""
+    rng = np.random.default_rng(1000 + rd + b + ell)
+    S = np.sort(10.0 ** rng.uniform(-3, 3, rd))[::-1].copy()
+    P = 1e-2 * rng.standard_normal((rd, b))
+    X = 1e-4 * rng.standard_normal((b, ell))
+    u, sig, v, kmat, pad = _block_rows_svd(sec, S, P, X)
+    c = rd + ell
+    ref = np.linalg.svd(kmat, compute_uv=False)
+    np.testing.assert_allclose(sig, ref, rtol=1e-10, atol=1e-15 * ref[0])
+    assert np.all(np.diff(sig) <= 0)
+    assert np.max(np.abs(pad), initial=0.0) <= 1e-13
+    np.testing.assert_allclose(u.T @ u, np.eye(c), atol=1e-13)
+    np.testing.assert_allclose(v.T @ v, np.eye(c), atol=1e-13)
+    np.testing.assert_allclose(u @ np.diag(sig) @ v.T, kmat, atol=4e-15 * ref[0] * np.sqrt(c))
