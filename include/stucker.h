@@ -333,8 +333,11 @@ int st_symeig(const double *a, int64_t n, double *w, double *q, int64_t k, void 
  * G has shape r_1 x ... x r_d, X and X^ have shape n_1 x ... x n_d, all
  * column-major float32 device arrays. factors is a host array of d device
  * pointers; U_k is column-major n_k x r_k float32. precision (enum
- * st_precision) selects the product arithmetic of every mode-k TTM; sums of
- * the factor gradients are FP64. work is a device workspace of at least the
+ * st_precision) selects the product arithmetic of every mode-k TTM and of the
+ * factor-gradient contractions (FP32, split-bf16 or FP64 products on the
+ * matrix cores; those sums run in FP32 within tiles of 32 fibres and in FP64
+ * across them, FP64 throughout for ST_FP64; modes with n_k + r_k above about
+ * 1280 take FP64 products). work is a device workspace of at least the
  * size st_tucker_workspace returns (the caller owns it; it holds factor copies
  * and the intermediate partial chains and may be reused across calls on one
  * stream). The work runs on stream (hipStream_t, NULL = null stream) and the

@@ -191,6 +191,127 @@ __global__ __launch_bounds__(256) void cross_kernel(const float *Y, const float 
   }
 }
 
+// The same contraction on the matrix cores, in the precision of the call: a
+// block stages kCrossMFT fibres of Y and B in LDS (zero past n, r and F) and
+// each wave accumulates TPW output tiles of 16 x 16 (the MFMA K dimension runs
+// over the fibres). FP32 products and sums (16x16x4 f32) or split-bf16 products
+// hi*hi + hi*lo + lo*hi (16x16x32 bf16) within one staged tile, whose sums are
+// then added in FP64; FP64 products and sums of the FP32 data (16x16x4 f64).
+// Partials per fibre block in FP64 like cross_kernel.
+constexpr int kCrossMFT = 32;
+constexpr int kCrossTPW = 4;  // output tiles per wave
+
+int cross_mfma_blocks_x(int64_t F) {
+  const int64_t t = (F + kCrossMFT - 1) / kCrossMFT;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(t, kCrossMaxBlocks));
+}
+
+size_t cross_mfma_lds(int64_t n, int64_t r) {
+  return (size_t)kCrossMFT * (16 * ((n + 15) / 16) + 16 * ((r + 15) / 16)) * sizeof(float);
+}
+
+template <int P>  // 0 FP32, 1 split bf16, 2 FP64
+__global__ __launch_bounds__(256) void cross_mfma_kernel(const float *Y, const float *B,
+                                                         int64_t a, int64_t n, int64_t r,
+                                                         int64_t F, double *part) {
+  extern __shared__ float sm[];
+  const int np = 16 * (int)((n + 15) / 16), rp = 16 * (int)((r + 15) / 16);
+  float *ys = sm;                   // [kCrossMFT][np]
+  float *bs = sm + kCrossMFT * np;  // [kCrossMFT][rp]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int tn = np / 16, ntiles = tn * (rp / 16);
+  const int tile0 = (int)blockIdx.y * 4 * kCrossTPW + wid * kCrossTPW;
+  double acc[kCrossTPW][4];
+#pragma unroll
+  for (int t = 0; t < kCrossTPW; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
+  const int64_t ftiles = (F + kCrossMFT - 1) / kCrossMFT;
+  for (int64_t ft = blockIdx.x; ft < ftiles; ft += gridDim.x) {
+    __syncthreads();
+    for (int idx = tid; idx < kCrossMFT * np; idx += 256) {
+      const int f = idx % kCrossMFT, i = idx / kCrossMFT;
+      const int64_t fib = ft * kCrossMFT + f;
+      float v = 0.0f;
+      if (fib < F && i < n) {
+        const int64_t hi = fib / a, lo = fib - hi * a;
+        v = Y[lo + a * n * hi + a * i];
+      }
+      ys[f * np + i] = v;
+    }
+    for (int idx = tid; idx < kCrossMFT * rp; idx += 256) {
+      const int f = idx % kCrossMFT, j = idx / kCrossMFT;
+      const int64_t fib = ft * kCrossMFT + f;
+      float v = 0.0f;
+      if (fib < F && j < r) {
+        const int64_t hi = fib / a, lo = fib - hi * a;
+        v = B[lo + a * r * hi + a * j];
+      }
+      bs[f * rp + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kCrossTPW; ++t) {
+      const int tile = tile0 + t;
+      if (tile >= ntiles) break;  // uniform per wave
+      const int i = 16 * (tile % tn) + col, j = 16 * (tile / tn) + col;
+      if constexpr (P == 2) {
+        f64x4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < kCrossMFT / 4; ++st) {
+          const int f = 4 * st + grp;
+          c = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ys[f * np + i], (double)bs[f * rp + j],
+                                                   c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] += c[v];
+      } else if constexpr (P == 0) {
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int st = 0; st < kCrossMFT / 4; ++st) {
+          const int f = 4 * st + grp;
+          c = __builtin_amdgcn_mfma_f32_16x16x4f32(ys[f * np + i], bs[f * rp + j], c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] += (double)c[v];
+      } else {
+        bf16x8 ah, al, bh, bl;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int f = 8 * grp + q;
+          const float x = ys[f * np + i], y = bs[f * rp + j];
+          const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+          ah[q] = xh;
+          al[q] = (__bf16)(x - (float)xh);
+          bh[q] = yh;
+          bl[q] = (__bf16)(y - (float)yh);
+        }
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] += (double)c[v];
+      }
+    }
+  }
+  // accumulator element v of lane (grp, col): row grp + 4 v (FP64) or 4 grp + v,
+  // column col of the tile
+  const int64_t nr = n * r;
+#pragma unroll
+  for (int t = 0; t < kCrossTPW; ++t) {
+    const int tile = tile0 + t;
+    if (tile >= ntiles) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = 16 * (tile % tn) + (P == 2 ? grp + 4 * v : 4 * grp + v);
+      const int64_t j = 16 * (tile / tn) + col;
+      if (i < n && j < r) part[(size_t)blockIdx.x * nr + i + n * j] = acc[t][v];
+    }
+  }
+}
+
 __global__ void cross_reduce_kernel(const double *part, int nb, int64_t nr, float *out) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= nr) return;
@@ -331,6 +452,34 @@ struct Run {
     const int64_t a = prod(p.r, 0, k), n = p.n[k], r = p.r[k];
     const int64_t F = a * prod(p.r, k + 1, p.d);
     const int64_t nr = n * r;
+    const size_t lm = cross_mfma_lds(n, r);
+    if (lm <= 160 * 1024) {
+      // matrix cores in the call's precision
+      const int nbx = cross_mfma_blocks_x(F);
+      const int64_t tiles = ((n + 15) / 16) * ((r + 15) / 16);
+      const unsigned nby = (unsigned)((tiles + 4 * kCrossTPW - 1) / (4 * kCrossTPW));
+      const void *fn = p.prec == Prec::FP64     ? (const void *)cross_mfma_kernel<2>
+                       : p.prec == Prec::BF16X3 ? (const void *)cross_mfma_kernel<1>
+                                                : (const void *)cross_mfma_kernel<0>;
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm);
+      if (e != hipSuccess) return e;
+      double *part = at<double>(p.part);
+      if (p.prec == Prec::FP64)
+        hipLaunchKernelGGL(cross_mfma_kernel<2>, dim3((unsigned)nbx, nby), dim3(256), lm, s, Y, B,
+                           a, n, r, F, part);
+      else if (p.prec == Prec::BF16X3)
+        hipLaunchKernelGGL(cross_mfma_kernel<1>, dim3((unsigned)nbx, nby), dim3(256), lm, s, Y, B,
+                           a, n, r, F, part);
+      else
+        hipLaunchKernelGGL(cross_mfma_kernel<0>, dim3((unsigned)nbx, nby), dim3(256), lm, s, Y, B,
+                           a, n, r, F, part);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(cross_reduce_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s,
+                         part, nbx, nr, out);
+      return hipGetLastError();
+    }
+    // very long modes (n + r above about 1280): FP64 products on the vector units
     const int nbx = cross_blocks_x(F);
     const unsigned nby = (unsigned)((nr + 256 * kCrossOPT - 1) / (256 * kCrossOPT));
     const size_t lds = (size_t)kCrossFT * (n + r) * sizeof(float);
