@@ -109,3 +109,58 @@ def test_block_isvd_middle_matrix_reproduces_the_rows():
     np.testing.assert_allclose(u_new @ np.diag(s_new) @ v_new.T, full, atol=1e-12)
     np.testing.assert_allclose(v_new.T @ v_new, np.eye(r + b), atol=1e-12)
     np.testing.assert_allclose(u_new.T @ u_new, np.eye(r + b), atol=1e-12)
+
+
+def _block_threshold_case(level, alpha=0.1, n=8, tau=0.1):
+    """Old data: two rank-one slices of norm alpha (ranks (2, 2, 2)). New block
+    of two slices, ||Y_B|| = 1, holding three orthogonal parts of norm
+    level * tau: one outside the mode-1 span (slice 1), one outside the mode-2
+    span and one inside both spans but outside the span of the streaming-mode
+    auxiliary matrix V (core coordinate (1, 2); slice 2)."""
+    q_, _ = np.linalg.qr(np.random.default_rng(31).standard_normal((n, 3)))
+    a1, a2, a3 = q_.T
+    q_, _ = np.linalg.qr(np.random.default_rng(32).standard_normal((n, 3)))
+    b1, b2, b3 = q_.T
+    x0 = np.stack([alpha * np.outer(a1, b1), alpha * np.outer(a2, b2)], axis=-1)
+    g = level * tau
+    m = np.sqrt((1.0 - 3.0 * g * g) / 2.0)
+    y1 = m * np.outer(a1, b1) + g * np.outer(a3, b1)
+    y2 = m * np.outer(a1, b1) + g * np.outer(a1, b3) + g * np.outer(a1, b2)
+    return x0, np.stack([y1, y2], axis=-1), tau
+
+
+@pytest.mark.parametrize("level", [0.60, 0.80])
+def test_block_tolerance_grows_residuals_above_tau_over_sqrt_d(level):
+    """eps_B = tau ||Y_B|| / sqrt(d) (d = 3): residual parts of level * tau
+    ||Y_B|| with level > 1/sqrt(3) grow both slice modes and the streaming rank,
+    and nothing is lost: once the slice modes hold the two outer parts, they
+    join the third as residual directions of the streaming mode (E^T E has
+    eigenvalues 2 g^2 and g^2, g = level tau, both above eps_B^2), so both are
+    kept. A tolerance of tau ||Y_B|| keeps the slice modes and loses
+    3 level^2 tau^2."""
+    x0, yb, tau = _block_threshold_case(level)
+    st = StreamingTucker(x0, tau)
+    rec = st.update_block(yb)
+    g = level * tau
+    assert rec["grew"] == [True, True] and rec["ell"] == 2
+    np.testing.assert_allclose(rec["lam"][:2], [2 * g * g, g * g], rtol=1e-12)
+    assert st.ranks == (3, 3, 4)
+    x = np.concatenate([x0, yb], axis=-1)
+    assert np.linalg.norm(x - st.reconstruct()) <= 1e-12
+
+
+@pytest.mark.parametrize("core_update", ["literal", "factored"])
+def test_block_tolerance_keeps_residuals_below_tau_over_sqrt_d(core_update):
+    """The converse: parts of 0.55 tau ||Y_B|| (below tau ||Y_B|| / sqrt(3))
+    grow nothing and the bound adds the three squared parts. A smaller block
+    tolerance (tau ||Y_B|| / sqrt(d b), or one from a single slice's norm
+    ||Y_B|| / sqrt(2) here) would grow all three."""
+    x0, yb, tau = _block_threshold_case(0.55)
+    st = StreamingTucker(x0, tau, core_update=core_update)
+    rec = st.update_block(yb)
+    assert rec["grew"] == [False, False] and rec["ell"] == 0
+    assert st.ranks == (2, 2, 2)
+    bound = st.recon_error_bound() * np.sqrt(st.xnorm2)
+    assert bound == pytest.approx(np.sqrt(3.0) * 0.55 * tau, rel=1e-9)
+    x = np.concatenate([x0, yb], axis=-1)
+    assert np.linalg.norm(x - st.reconstruct()) <= bound * (1 + 1e-12)
