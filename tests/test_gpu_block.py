@@ -118,3 +118,31 @@ def test_block_of_one_is_update_and_factored_is_refused():
         f.update_block(torch.from_numpy(np.concatenate(flat[6:9])).cuda(), 3)
     assert ei.value.code == ST_EINVAL
     assert f.ranks[-1] > 0
+
+
+@pytest.mark.parametrize("level", [0.55, 0.60, 0.80])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_block_threshold_decisions(level, precision):
+    """The oracle's block-tolerance pins (residual parts of level * tau ||Y_B||
+    in both slice modes and the streaming mode, eps_B = tau ||Y_B|| / sqrt(3))
+    through st_update_block: the same growth decisions and ranks, and the
+    certified bound up to the products' rounding."""
+    import torch
+
+    import paper_2308_16395_amd as pkg
+    from tests.test_oracle_block import _block_threshold_case
+
+    x0, yb, tau = _block_threshold_case(level)
+    orc = Oracle(x0, tau)
+    rec = orc.update_block(yb)
+    gpu = pkg.StreamingTucker(x0.shape[:-1], tau, precision=precision)
+    flat = lambda a: torch.from_numpy(  # noqa: E731
+        np.concatenate([vec(a[..., t]) for t in range(a.shape[-1])]).astype(np.float32)).cuda()
+    gpu.init(flat(x0), x0.shape[-1])
+    gpu.update_block(flat(yb), yb.shape[-1])
+    assert gpu.ranks == orc.ranks, (gpu.ranks, orc.ranks, rec["grew"], rec["ell"])
+    bound, _ = gpu.recon_error()
+    # FP32 Gram products leave rounding-level eigenvalues (about u32 ||E||^2)
+    # in the discarded tail: an absolute 5e-5 of ||X|| at tau = 0.1
+    atol = 1e-7 if precision == "fp64" else 5e-5
+    assert bound == pytest.approx(orc.recon_error_bound(), rel=1e-4, abs=atol)
