@@ -386,14 +386,15 @@ static size_t vectors_lds_bytes(int n) { return (size_t)n * n * sizeof(double); 
 
 bool eig_small_supported(int n) {
   if (n < 1 || n > kEigMaxN) return false;
-  static int limit = -1;
-  if (limit < 0) {
+  // the opt-in shared memory per block of the current device, queried once
+  // (a thread-safe static initialisation; the library runs one device type)
+  static const int limit = [] {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
       v = 0;
-    limit = v;
-  }
+    return v;
+  }();
   return vectors_lds_bytes(n) + 16384 <= (size_t)limit;
 }
 
