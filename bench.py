@@ -644,9 +644,12 @@ def main():
         def block_leg():
             out = dict(workload=f"same stream and window (slices {t_begin}..{t_end - 1}); "
                                 "blocks of b slices per st_update_block call, "
-                                f"{args.precision}, literal core")
-            for bsz in (4, 16):
-                st = pkg.StreamingTucker(stream.dims, w["tau"], precision=args.precision)
+                                f"{args.precision}; literal core (bN) and factored core "
+                                "(bN_factored)")
+            for bsz, core in ((4, "literal"), (16, "literal"), (4, "factored"),
+                              (16, "factored")):
+                st = pkg.StreamingTucker(stream.dims, w["tau"], precision=args.precision,
+                                         core_update=core)
                 st.init(data[:n_init].reshape(-1), n_init)
                 t = n_init
                 while t < t_begin:
@@ -666,7 +669,8 @@ def main():
                     rec = st.reconstruct_slice(tt)
                     err2 += torch.sum((rec.double() - data[tt].double()) ** 2).item()
                     nrm2 += torch.sum(data[tt].double() ** 2).item()
-                out[f"b{bsz}"] = dict(value=round((t_end - t_begin) / dt, 3),
+                key = f"b{bsz}" if core == "literal" else f"b{bsz}_factored"
+                out[key] = dict(value=round((t_end - t_begin) / dt, 3),
                                       ms_per_block=round(1e3 * dt / ((t_end - t_begin) / bsz), 3),
                                       ranks_final=list(st.ranks),
                                       recon_error_bound=st.recon_error()[0],

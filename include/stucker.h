@@ -211,12 +211,15 @@ int st_update(st_handle *h, const float *y);
  * sums over all b slices); the streaming mode generalises Alg. 3: both
  * Gram-Schmidt passes on every slice's core coordinates, the residual block's
  * directions kept by the TruncatedSVD of Alg. 1 (eigenpairs of E^T E, tail rule
- * against eps^2), the dense middle matrix [[diag S, 0], [P^T, W L^1/2]] with
- * the orthogonality check of [V Q] and its QR fix, and its SVD by one-sided
- * Jacobi. b = 1 is st_update. Literal core form only. n_d grows by b; st_stats
- * then reports, per block, q = the norm of the discarded residual directions.
- * Errors: ST_EINVAL (b < 1, factored core form), the errors of st_update; the
- * decomposition is unchanged on error, as for st_update. */
+ * against eps^2), the middle matrix [[diag S, 0], [P^T, W L^1/2]] with the
+ * orthogonality check of [V Q] and its QR fix; its SVD by b secular row
+ * appends to [diag S, 0] (one-sided Jacobi after a QR fix). Both core forms:
+ * the literal one rotates V and the core, the factored one (V = V0 M) appends
+ * Q to V0 and updates M and V0^T V0. b = 1 is st_update. n_d grows by b;
+ * st_stats then reports, per block, q = the norm of the discarded residual
+ * directions.
+ * Errors: ST_EINVAL (b < 1), the errors of st_update; the decomposition is
+ * unchanged on error, as for st_update. */
 int st_update_block(st_handle *h, const float *y, int64_t b);
 
 /* Current ranks r_1..r_d (ranks[0..d-1]) of the Tucker decomposition

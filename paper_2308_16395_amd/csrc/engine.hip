@@ -743,8 +743,6 @@ int st_handle::do_update(const float *y, int64_t bsz) {
   if (!inited) return fail(ST_ESTATE, "update before init");
   if (y == nullptr) return fail(ST_EINVAL, "null slice");
   if (bsz < 1) return fail(ST_EINVAL, "block of %lld slices", (long long)bsz);
-  if (bsz > 1 && factored)
-    return fail(ST_EINVAL, "block updates take the literal core form (ST_CORE_LITERAL)");
   const int d = m + 1;
   st_slice_stats stt{};
   int64_t rn[ST_MAX_MODES];
@@ -1645,13 +1643,34 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   const size_t nn2 = (size_t)n2 * n2;
   hipError_t e = hipSuccess;
   tic();
-  // V at the new row layout (the padded rows are zero)
+  // V at the new row layout (the padded rows are zero). In the factored form
+  // this is V0 (V = V0 M), relaid into the other V buffer, with room for the b
+  // columns a block may append, whenever the committed one cannot take them in
+  // place (the committed V0 is only ever written past its r_d columns).
   const double *Vn = V[cur].p;
-  if (!map.identity) {
+  int w0 = v0cur;
+  double *V0n = nullptr;
+  if (factored) {
+    const size_t need = (size_t)Rnew * (size_t)(rd + b);
+    if (!map.identity || V[v0cur].cap < need) {
+      w0 = v0cur ^ 1;
+      e = V[w0].ensure(std::max(need, (size_t)Rnew * (size_t)(rd + 16)));
+      if (e == hipSuccess) {
+        if (!map.identity)
+          e = launch_remap_rows(V[v0cur].p, Rold, map, Rnew, rdi, V[w0].p, stream);
+        else
+          e = hipMemcpyAsync(V[w0].p, V[v0cur].p, (size_t)Rold * rd * sizeof(double),
+                             hipMemcpyDeviceToDevice, stream);
+      }
+    }
+    V0n = V[w0].p;
+    Vn = V0n;
+  } else if (!map.identity) {
     e = bV.ensure((size_t)Rnew * std::max(rdi, 1));
     if (e == hipSuccess) e = launch_remap_rows(V[cur].p, Rold, map, Rnew, rdi, bV.p, stream);
     Vn = bV.p;
   }
+  const double *Mc = factored ? Mf[cur].p : nullptr;
   // small buffers: P1, P2, P (rd x b each), GE (b x b), Wsc (b x b), VQ (rd x b),
   // QQ (b x b), VtV (rd x rd), then G, K, W, Rpad, sig for the dense part
   const size_t rb_ = (size_t)rdi * bi, bb = (size_t)bi * bi;
@@ -1659,7 +1678,8 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
                off_vq = off_wsc + bb, off_qq = off_vq + rb_, off_vtv = off_qq + bb,
                off_g = off_vtv + (size_t)rdi * rdi, off_k = off_g + nn2, off_w = off_k + nn2,
                off_r = off_w + nn2, off_sig = off_r + nn2, off_ge2 = off_sig + n2 + bi,
-               off_gw = off_ge2 + bb, nsmall = off_gw + bb;
+               off_gw = off_ge2 + bb, off_tt = off_gw + bb, off_tw = off_tt + rb_,
+               off_tq = off_tw + rb_, nsmall = off_tq + rb_;
   if (e == hipSuccess) e = bsm.ensure(nsmall);
   if (e == hipSuccess) e = bE.ensure((size_t)Rnew * bi);
   if (e == hipSuccess) e = qstat.ensure(2);
@@ -1668,25 +1688,36 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
          *Wsc = bsm.p + off_wsc, *VQ = bsm.p + off_vq, *QQ = bsm.p + off_qq,
          *VtV = bsm.p + off_vtv, *G = bsm.p + off_g, *K = bsm.p + off_k, *Wj = bsm.p + off_w,
          *Rp = bsm.p + off_r, *sig = bsm.p + off_sig, *GE2 = bsm.p + off_ge2,
-         *GW = bsm.p + off_gw;
+         *GW = bsm.p + off_gw, *TT = bsm.p + off_tt, *TW = bsm.p + off_tw, *TQ = bsm.p + off_tq;
   const double one = 1.0, mone = -1.0, zero = 0.0;
   rocblas_status bs = rocblas_status_success;
   // two Gram-Schmidt passes on all b columns
+  // V^T X and V P: directly, or as M^T (V0^T X) and V0 (M P) in the factored form
+  auto vt_times = [&](const double *X, int cols, double *out) -> hipError_t {
+    if (!factored) return chunk_tn(Vn, Rnew, X, Rnew, Rnew, rdi, cols, out);
+    hipError_t ee = chunk_tn(V0n, Rnew, X, Rnew, Rnew, rdi, cols, TT);
+    if (ee == hipSuccess) ee = launch_small_gemm(1, Mc, rdi, TT, rdi, out, rdi, rdi, cols, rdi, stream);
+    return ee;
+  };
+  auto sub_v_times = [&](const double *Pm, double *X) -> rocblas_status {
+    const double *F = Pm;
+    if (factored) {
+      if (launch_small_gemm(0, Mc, rdi, Pm, rdi, TW, rdi, rdi, bi, rdi, stream) != hipSuccess)
+        return rocblas_status_internal_error;
+      F = TW;
+    }
+    return rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew,
+                         bi, rdi, &mone, Vn, (rocblas_int)Rnew, F, rdi, &one, X,
+                         (rocblas_int)Rnew);
+  };
   if (rdi > 0) {
-    e = chunk_tn(Vn, Rnew, Dm, Rnew, Rnew, rdi, bi, P1);
+    e = vt_times(Dm, bi, P1);
     if (e == hipSuccess)
       e = hipMemcpyAsync(bE.p, Dm, (size_t)Rnew * bi * sizeof(double), hipMemcpyDeviceToDevice,
                          stream);
-    if (e == hipSuccess)
-      bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew,
-                         bi, rdi, &mone, Vn, (rocblas_int)Rnew, P1, rdi, &one, bE.p,
-                         (rocblas_int)Rnew);
-    if (e == hipSuccess && bs == rocblas_status_success)
-      e = chunk_tn(Vn, Rnew, bE.p, Rnew, Rnew, rdi, bi, P2);
-    if (e == hipSuccess && bs == rocblas_status_success)
-      bs = rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)Rnew,
-                         bi, rdi, &mone, Vn, (rocblas_int)Rnew, P2, rdi, &one, bE.p,
-                         (rocblas_int)Rnew);
+    if (e == hipSuccess) bs = sub_v_times(P1, bE.p);
+    if (e == hipSuccess && bs == rocblas_status_success) e = vt_times(bE.p, bi, P2);
+    if (e == hipSuccess && bs == rocblas_status_success) bs = sub_v_times(P2, bE.p);
     if (e == hipSuccess) e = launch_vadd(P1, P2, (int64_t)rb_, Pv, stream);
   } else {
     e = hipMemcpyAsync(bE.p, Dm, (size_t)Rnew * bi * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1733,8 +1764,12 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   e = U2.ensure(nn2);
   if (e == hipSuccess) e = V2.ensure(nn2);
   if (e == hipSuccess) e = S[nxt].ensure((size_t)n2);
-  if (e == hipSuccess) e = V[nxt].ensure((size_t)Rnew * std::max(c, 1));
-  if (e == hipSuccess) e = C[nxt].ensure((size_t)Rnew * std::max(c, 1));
+  // (the factored form keeps V0 in V[w0] and no core: its V buffers follow
+  // v0cur, not cur, and must not be reallocated here)
+  if (e == hipSuccess && !factored) e = V[nxt].ensure((size_t)Rnew * std::max(c, 1));
+  if (e == hipSuccess && !factored) e = C[nxt].ensure((size_t)Rnew * std::max(c, 1));
+  if (e == hipSuccess && factored) e = Mf[nxt].ensure((size_t)c * c);
+  if (e == hipSuccess && factored) e = Gf[nxt].ensure((size_t)c * c);
   if (e == hipSuccess) e = bQ.ensure((size_t)Rnew * std::max(ell, 1));
   int64_t ldn = ud_ld[nxt];
   if (e == hipSuccess && (ldn < nd + b || Ud[nxt].cap < (size_t)ldn * c)) {
@@ -1752,7 +1787,16 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
                          ell, bi, &one, bE.p, (rocblas_int)Rnew, Wsc, bi, &zero, bQ.p,
                          (rocblas_int)Rnew);
     if (bs != rocblas_status_success) return fail(ST_EHIP, "block basis GEMM failed");
-    if (e == hipSuccess && rdi > 0) e = chunk_tn(Vn, Rnew, bQ.p, Rnew, Rnew, rdi, ell, VQ);
+    if (e == hipSuccess && rdi > 0) {
+      if (factored) {
+        // V0^T Q also extends G0 at the commit
+        e = chunk_tn(V0n, Rnew, bQ.p, Rnew, Rnew, rdi, ell, TQ);
+        if (e == hipSuccess)
+          e = launch_small_gemm(1, Mc, rdi, TQ, rdi, VQ, rdi, rdi, ell, rdi, stream);
+      } else {
+        e = chunk_tn(Vn, Rnew, bQ.p, Rnew, Rnew, rdi, ell, VQ);
+      }
+    }
     if (e == hipSuccess) e = chunk_tn(bQ.p, Rnew, bQ.p, Rnew, Rnew, ell, ell, QQ);
     if (e == hipSuccess)
       e = launch_gather3(hpin_dev, VQ, rdi * ell, 0, QQ, ell * ell, rdi * ell, nullptr, 0, 0,
@@ -1771,7 +1815,16 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   // middle matrix (zero-padded to n2 x n2), with the QR fix when the check fired
   e = launch_block_k(S[cur].p, Pv, rdi, bi, GW, bi, sig, ell, K, stream);
   if (e == hipSuccess && stt.qr_fired) {
-    if (rdi > 0) e = chunk_tn(Vn, Rnew, Vn, Rnew, Rnew, rdi, rdi, VtV);
+    if (rdi > 0 && factored) {
+      // V^T V = M^T G0 M
+      e = qrg.ensure((size_t)rdi * rdi);
+      if (e == hipSuccess)
+        e = launch_small_gemm(0, Gf[cur].p, rdi, Mc, rdi, qrg.p, rdi, rdi, rdi, rdi, stream);
+      if (e == hipSuccess)
+        e = launch_small_gemm(1, Mc, rdi, qrg.p, rdi, VtV, rdi, rdi, rdi, rdi, stream);
+    } else if (rdi > 0) {
+      e = chunk_tn(Vn, Rnew, Vn, Rnew, Rnew, rdi, rdi, VtV);
+    }
     if (e == hipSuccess) e = launch_gram_block_fill(VtV, rdi, VQ, QQ, ell, G, stream);
     if (e == hipSuccess) e = launch_chol_upper(G, c, qstat.p, stream);
     if (e == hipSuccess) e = launch_right_mul_rt(K, n2, G, c, stream);
@@ -1801,6 +1854,23 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   settle();
   if (st2[0] == 1) return fail(ST_ESOLVER, "QR fix: the Gram of [V Q] is not positive definite");
   if (st2[0] == 2) return fail(ST_ESOLVER, "block middle matrix: Jacobi SVD did not converge");
+  if (factored) {
+    // [V Q] V'' = [V0 Q] diag(M, I) V'': Q becomes columns rd..c-1 of V0,
+    // M~ = [M V''(0:rd, :); V''(rd:c, :)] and G0~ = [[G0, V0^T Q], [Q^T V0, Q^T Q]]
+    tic();
+    if (ell > 0)
+      e = hipMemcpyAsync(V0n + (size_t)Rnew * rdi, bQ.p, (size_t)Rnew * ell * sizeof(double),
+                         hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && rdi > 0)
+      e = launch_small_gemm(0, Mc, rdi, V2.p, n2, Mf[nxt].p, c, rdi, c, rdi, stream);
+    if (e == hipSuccess && ell > 0)
+      e = hipMemcpy2DAsync(Mf[nxt].p + rdi, (size_t)c * sizeof(double), V2.p + rdi,
+                           (size_t)n2 * sizeof(double), (size_t)ell * sizeof(double), c,
+                           hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = launch_gram_block_fill(Gf[cur].p, rdi, TQ, QQ, ell, Gf[nxt].p, stream);
+    toc(ST_K_SVD, 2.0 * (double)rdi * rdi * c, 8.0 * (Rnew * (double)ell + 2.0 * c * c));
+    if (e != hipSuccess) return hipfail(e, "block factored update");
+  } else {
   // V~ = V V''(0:rd, :) + Q V''(rd:c, :)
   tic();
   if (rdi > 0)
@@ -1831,6 +1901,7 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   toc(ST_K_ROT_C, 2.0 * Rnew * (double)(rdi + b) * c, 4.0 * Rold * rdi + 8.0 * Rnew * b + 4.0 * Rnew * c);
   if (bs != rocblas_status_success) return fail(ST_EHIP, "block core GEMM failed");
   if (e != hipSuccess) return hipfail(e, "block core update");
+  }
   tic();
   e = launch_ud_update_block(Ud[cur].p, ud_ld[cur], nd, rdi, bi, U2.p, n2, c, Ud[nxt].p, ldn,
                              stream);
@@ -1846,6 +1917,7 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   rd = c;
   nd += b;
   cur = nxt;
+  if (factored) v0cur = w0;
   xnorm2 += ynorm2;
   delta2 += tail;
   disc += delta2;

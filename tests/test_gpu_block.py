@@ -3,7 +3,8 @@ the oracle's update_block on the same float32 slices: ranks after every block,
 the number of kept residual directions, reconstructions of probe slices
 (within 1e-5 of the slice norm: the literal core is stored in FP32), the
 singular values and the certified bound; a ragged last block; the forced QR
-fix of the block orthogonality check; b = 1 against the single-slice update.
+fix of the block orthogonality check; b = 1 against the single-slice update;
+the factored core form; threshold blocks.
 """
 
 import numpy as np
@@ -17,14 +18,16 @@ from tests._parity import slices32
 pytestmark = pytest.mark.gpu
 
 
-def _run(s, n, n_init, tau, bsize, precision="fp64", orth_tol=0.0, eps_m=1e-12):
+def _run(s, n, n_init, tau, bsize, precision="fp64", orth_tol=0.0, eps_m=1e-12,
+         core_update="literal"):
     import torch
 
     import paper_2308_16395_amd as pkg
 
     flat, shaped = slices32(s, n)
-    orc = Oracle(np.stack(shaped[:n_init], axis=-1), tau, eps_m=eps_m)
-    gpu = pkg.StreamingTucker(s.dims, tau, precision=precision, orth_tol=orth_tol)
+    orc = Oracle(np.stack(shaped[:n_init], axis=-1), tau, eps_m=eps_m, core_update=core_update)
+    gpu = pkg.StreamingTucker(s.dims, tau, precision=precision, orth_tol=orth_tol,
+                              core_update=core_update)
     gpu.init(torch.from_numpy(np.concatenate(flat[:n_init])).cuda(), n_init)
     assert gpu.ranks == orc.ranks
     worst, t, stats = 0.0, n_init, []
@@ -93,11 +96,10 @@ def test_block_qr_fix_forced():
     assert torch.max(torch.abs(g - torch.eye(g.shape[0], device=g.device, dtype=g.dtype))) < 1e-8
 
 
-def test_block_of_one_is_update_and_factored_is_refused():
+def test_block_of_one_is_update():
     import torch
 
     import paper_2308_16395_amd as pkg
-    from paper_2308_16395_amd.binding import ST_EINVAL, StError
 
     s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=20, seed=21)
     flat, _ = slices32(s, 20)
@@ -112,12 +114,42 @@ def test_block_of_one_is_update_and_factored_is_refused():
         b.update_block(y, 1)
         assert a.ranks == b.ranks
     np.testing.assert_array_equal(np.asarray(a.sv()), np.asarray(b.sv()))
-    f = pkg.StreamingTucker(s.dims, 1e-3, core_update="factored")
-    f.init(x0, 6)
-    with pytest.raises(StError) as ei:
-        f.update_block(torch.from_numpy(np.concatenate(flat[6:9])).cuda(), 3)
-    assert ei.value.code == ST_EINVAL
-    assert f.ranks[-1] > 0
+
+
+@pytest.mark.parametrize("precision,bsize", [("fp64", 3), ("fp64", 4), ("fp32", 5)])
+def test_block_updates_factored(precision, bsize):
+    """The factored core form (V = V0 M): the block's residual directions Q are
+    appended to V0 and M, G0 = V0^T V0 extended; against the oracle's factored
+    block updates."""
+    s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=36, seed=21)
+    gpu, orc, worst, stats = _run(s, 36, 6, 1e-3, bsize, precision=precision,
+                                  core_update="factored")
+    assert worst <= 1e-5, worst
+    _check_s_and_bound(gpu, orc, 1e-9 if precision == "fp64" else 1e-5)
+    assert sum(rec["ell"] for _, rec in stats) > 5
+    # V = V0 M stays orthonormal
+    import torch
+
+    v = gpu.aux_v()
+    g = v.T @ v
+    assert torch.max(torch.abs(g - torch.eye(g.shape[0], device=g.device, dtype=g.dtype))) < 1e-9
+
+
+def test_block_updates_factored_medium_stream_and_qr_fix():
+    """48^3 x 8 blobs in blocks of 4 in the factored form; then the forced QR
+    fix of the block orthogonality check in the factored form."""
+    s = BlobStream((48, 48, 48), 8, 16, (3.0, 8.0), 0.5, n_slices=42, seed=41)
+    gpu, orc, worst, _ = _run(s, 42, 10, 1e-4, 4, core_update="factored")
+    assert worst <= 1e-5, worst
+    _check_s_and_bound(gpu, orc, 1e-9)
+    s = BlobStream((24, 20, 16), 3, 6, (2.0, 5.0), 0.7, n_slices=36, seed=21)
+    gpu, orc, worst, stats = _run(s, 36, 6, 1e-3, 3, orth_tol=1e-300, eps_m=0.0,
+                                  core_update="factored")
+    fired_gpu = [bool(st["qr_fired"]) for st, _ in stats]
+    fired_orc = [bool(rec["qr"]) for _, rec in stats]
+    assert fired_gpu == fired_orc and sum(fired_gpu) >= 5
+    assert worst <= 1e-5, worst
+    _check_s_and_bound(gpu, orc, 1e-9)
 
 
 @pytest.mark.parametrize("level", [0.55, 0.60, 0.80])
