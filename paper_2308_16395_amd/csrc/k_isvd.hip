@@ -1061,10 +1061,23 @@ __device__ inline void mv_trans(const double *M, int r, const double *x, double 
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double t = wave_sum(a[c]);
+      const double t = dpp_wave_sum(a[c]);
       if (lane == 0 && i0 + c < r) y[i0 + c] = t;
     }
   }
+}
+
+// Block-wide sum with DPP wave sums (every thread active), the result in every
+// thread; scratch holds one double per wave.
+__device__ inline double block_sum_dpp(double v, double *scratch) {
+  const int nw = (int)(blockDim.x >> 6);
+  v = dpp_wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = scratch[0];
+  for (int w = 1; w < nw; ++w) t += scratch[w];
+  return t;
 }
 
 // y = M x (M column-major r x r). For r <= kMvRows the block's 16 waves split
@@ -1135,8 +1148,8 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
     a1 += w1[i] * t1[i];
     a2 += w1[i] * g[i];
   }
-  a1 = block_sum(a1, red);
-  a2 = block_sum(a2, red);
+  a1 = block_sum_dpp(a1, red);
+  a2 = block_sum_dpp(a2, red);
   const double e1sq = given ? sc[0] : dd[0] - 2.0 * a1 + a2;
   __syncthreads();
   mv_trans(M, r, t2, p2);
@@ -1153,8 +1166,8 @@ __global__ __launch_bounds__(1024) void isvd_gram_kernel(const double *M, const 
     b1 += w2[i] * t2[i];
     b2 += w2[i] * g[i];
   }
-  b1 = block_sum(b1, red);
-  b2 = block_sum(b2, red);
+  b1 = block_sum_dpp(b1, red);
+  b2 = block_sum_dpp(b2, red);
   if (tid == 0) {
     sc[0] = e1sq;
     sc[1] = e1sq - 2.0 * b1 + b2;
