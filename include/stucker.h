@@ -213,7 +213,9 @@ int st_update(st_handle *h, const float *y);
  * directions kept by the TruncatedSVD of Alg. 1 (eigenpairs of E^T E, tail rule
  * against eps^2), the middle matrix [[diag S, 0], [P^T, W L^1/2]] with the
  * orthogonality check of [V Q] and its QR fix; its SVD by b secular row
- * appends to [diag S, 0] (one-sided Jacobi after a QR fix). Both core forms:
+ * appends to [diag S, 0] (after a QR fix [V Q] = Q_f R, K R^T = U_K (R V_K
+ * diag(S_K))^T, and a one-sided Jacobi on that nearly orthogonal c x c
+ * factor). Both core forms:
  * the literal one rotates V and the core, the factored one (V = V0 M) appends
  * Q to V0 and updates M and V0^T V0. b = 1 is st_update. n_d grows by b;
  * st_stats then reports, per block, q = the norm of the discarded residual

@@ -537,7 +537,8 @@ struct st_handle {
   int exact_coords(const float *y, const double **dout);
   int do_init(const float *x0, int64_t n_init);
   int do_update(const float *y, int64_t b = 1);
-  hipError_t block_rows_svd(const double *K, int n2, int rdi, int bi, int c, double tol, int nxt);
+  hipError_t block_rows_svd(const double *K, int n2, int rdi, int bi, int c, double tol,
+                            double *Uo, double *Vo, double *So);
   int stream_block(const RowMap &map, const double *Dm, int64_t b, int64_t Rold, int64_t Rnew,
                    double eps, st_slice_stats &stt, const int64_t *rn, double delta2,
                    double ynorm2, double ms_modes, clk::time_point t0);
@@ -1601,9 +1602,9 @@ hipError_t st_handle::chunk_tn(const double *X, int64_t ldx, const double *Y, in
 // single-slice update with no new column; VK and UK take its factors
 // (VK <- VK V'', UK <- [[UK, 0], [0, 1]] U''). The l zero columns of [diag(S), 0]
 // are poles at zero, deflated while their weights vanish. Writes U'' and V''
-// (ld n2) and S[nxt].
+// into Uo ((rd + b) x c) and Vo (c x c), both ld n2, and So (c).
 hipError_t st_handle::block_rows_svd(const double *K, int n2, int rdi, int bi, int c, double tol,
-                                     int nxt) {
+                                     double *Uo, double *Vo, double *So) {
   const int ldv = c + 1, ldu = c + bi;
   const size_t nv = (size_t)ldv * c, nu = (size_t)ldu * c;
   hipError_t e = bsec.ensure(4 * nv + 2 * nu + 3 * (size_t)c);
@@ -1628,8 +1629,7 @@ hipError_t st_handle::block_rows_svd(const double *K, int n2, int rdi, int bi, i
     k ^= 1;
   }
   if (e == hipSuccess)
-    e = launch_block_rows_finish(VK[k], ldv, UK[k], ldu, sg[k], rdi, bi, c, V2.p, U2.p,
-                                 S[nxt].p, stream);
+    e = launch_block_rows_finish(VK[k], ldv, UK[k], ldu, sg[k], rdi, bi, c, Vo, Uo, So, stream);
   return e;
 }
 
@@ -1679,7 +1679,9 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
                off_g = off_vtv + (size_t)rdi * rdi, off_k = off_g + nn2, off_w = off_k + nn2,
                off_r = off_w + nn2, off_sig = off_r + nn2, off_ge2 = off_sig + n2 + bi,
                off_gw = off_ge2 + bb, off_tt = off_gw + bb, off_tw = off_tt + rb_,
-               off_tq = off_tw + rb_, nsmall = off_tq + rb_;
+               off_tq = off_tw + rb_, off_x1 = off_tq + rb_, off_x2 = off_x1 + nn2,
+               off_jp = off_x2 + nn2, off_jps = off_jp + nn2, off_sk = off_jps + nn2,
+               nsmall = off_sk + n2;
   if (e == hipSuccess) e = bsm.ensure(nsmall);
   if (e == hipSuccess) e = bE.ensure((size_t)Rnew * bi);
   if (e == hipSuccess) e = qstat.ensure(2);
@@ -1688,7 +1690,9 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
          *Wsc = bsm.p + off_wsc, *VQ = bsm.p + off_vq, *QQ = bsm.p + off_qq,
          *VtV = bsm.p + off_vtv, *G = bsm.p + off_g, *K = bsm.p + off_k, *Wj = bsm.p + off_w,
          *Rp = bsm.p + off_r, *sig = bsm.p + off_sig, *GE2 = bsm.p + off_ge2,
-         *GW = bsm.p + off_gw, *TT = bsm.p + off_tt, *TW = bsm.p + off_tw, *TQ = bsm.p + off_tq;
+         *GW = bsm.p + off_gw, *TT = bsm.p + off_tt, *TW = bsm.p + off_tw, *TQ = bsm.p + off_tq,
+         *X1 = bsm.p + off_x1, *X2 = bsm.p + off_x2, *Jp = bsm.p + off_jp, *JpS = bsm.p + off_jps,
+         *sK = bsm.p + off_sk;
   const double one = 1.0, mone = -1.0, zero = 0.0;
   rocblas_status bs = rocblas_status_success;
   // two Gram-Schmidt passes on all b columns
@@ -1814,6 +1818,12 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
   }
   // middle matrix (zero-padded to n2 x n2), with the QR fix when the check fired
   e = launch_block_k(S[cur].p, Pv, rdi, bi, GW, bi, sig, ell, K, stream);
+  // With an old basis K keeps its structure (diag(S) over b rows) and its SVD
+  // comes from the row appends; the QR fix then rotates those factors (K R^T =
+  // U_K (R V_K diag(S_K))^T, whose right factor has columns orthogonal up to the
+  // deviation the check measured, so the Jacobi on it ends in a sweep or two).
+  // An empty old basis takes the dense one-sided Jacobi SVD of K (R^T).
+  const bool by_rows = rdi > 0 && c <= kQrOrderMax;
   if (e == hipSuccess && stt.qr_fired) {
     if (rdi > 0 && factored) {
       // V^T V = M^T G0 M
@@ -1827,18 +1837,27 @@ int st_handle::stream_block(const RowMap &map, const double *Dm, int64_t b, int6
     }
     if (e == hipSuccess) e = launch_gram_block_fill(VtV, rdi, VQ, QQ, ell, G, stream);
     if (e == hipSuccess) e = launch_chol_upper(G, c, qstat.p, stream);
-    if (e == hipSuccess) e = launch_right_mul_rt(K, n2, G, c, stream);
-    if (e == hipSuccess) e = launch_pad_upper(G, c, n2, Rp, stream);
+    if (e == hipSuccess && !by_rows) e = launch_right_mul_rt(K, n2, G, c, stream);
+    if (e == hipSuccess && !by_rows) e = launch_pad_upper(G, c, n2, Rp, stream);
   } else if (e == hipSuccess) {
     e = hipMemsetAsync(qstat.p, 0, 2 * sizeof(int), stream);
   }
-  // K keeps its structure (diag(S) over b rows) unless the QR fix multiplied it
-  // by R^T: then, and for an empty old basis, the dense one-sided Jacobi SVD
-  const bool by_rows = !stt.qr_fired && rdi > 0;
   if (by_rows) {
     const double tol =
         8.0 * 0x1p-53 * std::max(S_host.empty() ? 0.0 : S_host[0], std::sqrt(ynorm2));
-    if (e == hipSuccess) e = block_rows_svd(K, n2, rdi, bi, c, tol, nxt);
+    if (!stt.qr_fired) {
+      if (e == hipSuccess) e = block_rows_svd(K, n2, rdi, bi, c, tol, U2.p, V2.p, S[nxt].p);
+    } else {
+      // U_K, V_K, S_K into X1, X2, sK; A = R V_K diag(S_K) over K (read by then)
+      if (e == hipSuccess) e = block_rows_svd(K, n2, rdi, bi, c, tol, X1, X2, sK);
+      if (e == hipSuccess) e = launch_form_rvs(G, c, X2, n2, sK, K, stream);
+      if (e == hipSuccess) e = launch_jacobi_svd(K, c, Wj, 60, qstat.p, stream);
+      if (e == hipSuccess) e = launch_qr_order(K, Wj, c, sK, S[nxt].p, Jp, JpS, stream);
+      if (e == hipSuccess)
+        e = launch_small_gemm(0, X1, n2, Jp, c, U2.p, n2, n2, c, c, stream);
+      if (e == hipSuccess)
+        e = launch_small_gemm(0, X2, n2, JpS, c, V2.p, n2, c, c, c, stream);
+    }
     toc(ST_K_SVD, b * (60.0 * (double)c * c + 4.0 * (double)c * c * c + 2.0 * (double)c * c * b),
         8.0 * b * (4.0 * (double)c * c + (double)c * (c + b)));
   } else {

@@ -483,6 +483,80 @@ hipError_t launch_block_rows_finish(const double *VK, int ldv, const double *UK,
   return hipGetLastError();
 }
 
+// A (c x c, ld c) = R V diag(s): R upper triangular (c x c, ld c), V (c x c,
+// ld ldv). The QR fix of a block: with K = U_K diag(s) V^T from the row
+// appends, K R^T = U_K A^T, and the columns of A are orthogonal up to the
+// deviation of [V Q] from orthonormality (a_i^T a_j = s_i s_j v_i^T R^T R v_j).
+__global__ void form_rvs_kernel(const double *R, int c, const double *V, int ldv,
+                                const double *sv, double *A) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c * c) return;
+  const int i = idx % c, j = idx / c;
+  double acc = 0.0;
+  for (int k = i; k < c; ++k) acc += R[i + (size_t)c * k] * V[k + (size_t)ldv * j];
+  A[idx] = acc * sv[j];
+}
+
+hipError_t launch_form_rvs(const double *R, int c, const double *V, int ldv, const double *sv,
+                           double *A, hipStream_t s) {
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(form_rvs_kernel, dim3((unsigned)((c * c + 255) / 256)), dim3(256), 0, s, R,
+                     c, V, ldv, sv, A);
+  return hipGetLastError();
+}
+
+// After the one-sided Jacobi on A = R V_K diag(sK) (A J has orthogonal columns
+// of norms sigma'): K R^T = (U_K J) diag(sigma') (A J diag(1/sigma'))^T, and
+// R^{-1} A J = V_K diag(sK) J, so the QR-fixed factors are U'' = U_K Jp and
+// V'' = V_K JpS with Jp = J's columns by descending sigma' (ties by index) and
+// JpS = diag(sK) Jp diag(1/sigma'). One block of 1024 threads, c <= 1024: the
+// column norms one wave per column, the order one thread per column (a NaN
+// sorts last, so the order is a permutation whatever the values), then Jp,
+// JpS (c x c, ld c) and Snew[0:c].
+__global__ __launch_bounds__(1024) void qr_order_kernel(const double *A, const double *J, int c,
+                                                        const double *sK, double *Snew,
+                                                        double *Jp, double *JpS) {
+  __shared__ double sg[kQrOrderMax];
+  __shared__ int perm[kQrOrderMax];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = wid; j < c; j += nw) {
+    double s2 = 0.0;
+    for (int k = lane; k < c; k += 64) {
+      const double a = A[k + (size_t)c * j];
+      s2 += a * a;
+    }
+    s2 = dpp_wave_sum(s2);
+    if (lane == 0) sg[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < c; j += blockDim.x) {
+    const double sj = sg[j];
+    const double kj = sj == sj ? sj : -1.0;
+    int o = 0;
+    for (int l = 0; l < c; ++l) {
+      const double kl = sg[l] == sg[l] ? sg[l] : -1.0;
+      o += (kl > kj || (kl == kj && l < j)) ? 1 : 0;
+    }
+    perm[o] = j;
+    Snew[o] = sj;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < c * c; idx += blockDim.x) {
+    const int k = idx % c, j = perm[idx / c];
+    const double v = J[k + (size_t)c * j], sj = sg[j];
+    Jp[idx] = v;
+    JpS[idx] = sj > 0.0 ? sK[k] * v / sj : 0.0;
+  }
+}
+
+hipError_t launch_qr_order(const double *A, const double *J, int c, const double *sK,
+                           double *Snew, double *Jp, double *JpS, hipStream_t s) {
+  if (c <= 0) return hipSuccess;
+  if (c > kQrOrderMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(qr_order_kernel, dim3(1), dim3(1024), 0, s, A, J, c, sK, Snew, Jp, JpS);
+  return hipGetLastError();
+}
+
 // dst (Rn x cols, FP64) = src (FP32, old row layout, ld ld_src) through the row map
 __global__ void remap_rows_f32_kernel(const float *src, int64_t ld_src, RowMap map, int64_t Rn,
                                       int cols, double *dst) {

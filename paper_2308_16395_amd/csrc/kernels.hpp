@@ -135,6 +135,14 @@ hipError_t launch_eig_tridiag(const double *A, int n, double *work, hipStream_t 
 hipError_t launch_eig_values(const double *work, int n, double *w, hipStream_t s);
 hipError_t launch_eig_vectors(const double *work, int n, const double *w, int k, double *Q,
                               int64_t ldq, int desc_cols, hipStream_t s);
+// QR fix of a block from the row appends' SVD (k_dense.hip): A = R V diag(s)
+// (R upper, ld c; V ld ldv), and after the Jacobi on A the ordered rotations
+// Jp and JpS with the new singular values (c <= kQrOrderMax).
+constexpr int kQrOrderMax = 1024;
+hipError_t launch_form_rvs(const double *R, int c, const double *V, int ldv, const double *sv,
+                           double *A, hipStream_t s);
+hipError_t launch_qr_order(const double *A, const double *J, int c, const double *sK,
+                           double *Snew, double *Jp, double *JpS, hipStream_t s);
 // Block middle-matrix SVD by row appends (k_dense.hip): start, rotated row, finish.
 hipError_t launch_block_rows_init(const double *S, int rd, int c, double *VK, int ldv, double *UK,
                                   int ldu, double *sig, hipStream_t s);
