@@ -24,6 +24,7 @@
 // Symmetric Eigenvalue Problem, 1980, chapters 7 and 4). The eigenvalues carry
 // an absolute error of a few u ||A||, the vectors u ||A|| / gap, as for any
 // backward-stable method.
+#include <algorithm>
 #include <cfloat>
 
 #include "common.hpp"
@@ -253,16 +254,21 @@ __global__ __launch_bounds__(256) void eig_values_kernel(const double *__restric
 // depend on the running values, so they are issued ahead), the block the
 // vector operations; then the reflections, staged in LDS, are applied by every
 // wave.
+// With k > 1, vectors whose eigenvalue is isolated (gap above gap_tol to both
+// kept neighbours) need no orthogonalisation: they are found in parallel first, one
+// thread each, kb at a time, with their right-hand sides and LU factors in the
+// dynamic LDS (interleaved by vector) before it takes the reflections. The
+// vectors of clusters follow one at a time, as above, with CGS2 in the cluster.
 __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restrict__ work, int n,
                                                          const double *__restrict__ w, int k,
-                                                         double *Q, int64_t ldq, int desc_cols) {
+                                                         double *Q, int64_t ldq, int desc_cols,
+                                                         int kb) {
   __shared__ double sd[kEigMaxN], se[kEigMaxN], lm[kEigMaxN], ri[kEigMaxN], ua[kEigMaxN],
       ub[kEigMaxN], pv[kEigMaxN], xs[kEigMaxN], coef[kEigMaxN], red[4];
-  extern __shared__ double vh[];  // n x n reflections
+  extern __shared__ double vh[];  // the isolated vectors' scratch, then n x n reflections
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const double *beta = work + (size_t)n * n, *dd = beta + n, *ee = dd + n;
   auto colq = [&](int c) { return Q + ldq * (desc_cols ? c : n - 1 - c); };
-  for (int idx = tid; idx < n * n; idx += blockDim.x) vh[idx] = work[idx];
   for (int i = tid; i < n; i += blockDim.x) {
     sd[i] = dd[i];
     se[i] = (i + 1 < n) ? ee[i] : 0.0;
@@ -271,6 +277,86 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
                     2.0 * bmax(tid + 1 < n ? fabs(ee[tid]) : 0.0, red);
   const double gap_tol = 1e-3 * tn, sep = 10.0 * kU * tn;
   const double tiny = fmax(kU * tn, DBL_MIN);
+  // vector c opens a cluster when its gap to vector c - 1 exceeds gap_tol
+  auto opens = [&](int c) { return c == 0 || w[n - c] - w[n - 1 - c] > gap_tol; };
+  // (a lone vector, k = 1, takes the block-wide loop below: one thread's serial
+  // normalisation costs more than the block reductions there)
+  auto isolated = [&](int c) { return k > 1 && opens(c) && (c + 1 >= k || opens(c + 1)); };
+  for (int b0 = 0; b0 < k && k > 1; b0 += kb) {
+    // the batch's start vectors, by all threads (X(i, t) at vh[i kb + t])
+    for (int idx = tid; idx < n * kb; idx += blockDim.x)
+      if (b0 + idx % kb < k) vh[idx] = start_value(idx / kb, b0 + idx % kb);
+    __syncthreads();
+    const int t = tid, c = b0 + tid;
+    if (t < kb && c < k && isolated(c)) {
+      double *X = vh + t, *Lm = X + (size_t)n * kb, *Ri = Lm + (size_t)n * kb,
+             *Ua = Ri + (size_t)n * kb, *Ub = Ua + (size_t)n * kb, *Pv = Ub + (size_t)n * kb;
+      const double lam = w[n - 1 - c];
+      // T - lam I = P L U, as below
+      double p = sd[0] - lam, q = se[0];
+      for (int kk = 0; kk + 1 < n; ++kk) {
+        const double dn = sd[kk + 1] - lam, ek = se[kk], en = se[kk + 1];
+        const bool sw = fabs(p) < fabs(ek);
+        const double pz = (!sw && p == 0.0) ? tiny : p;
+        const double r1 = recip(sw ? ek : pz);
+        const double l = (sw ? pz : ek) * r1;
+        const size_t o = (size_t)kk * kb;
+        Lm[o] = l;
+        Ri[o] = r1;
+        Ua[o] = sw ? dn : q;
+        Ub[o] = sw ? en : 0.0;
+        Pv[o] = sw ? 1.0 : 0.0;
+        const double pn = sw ? fma(-l, dn, q) : fma(-l, q, dn);
+        q = sw ? -l * en : en;
+        p = pn;
+      }
+      p = (fabs(p) < tiny) ? ((p < 0.0) ? -tiny : tiny) : p;
+      const size_t ol = (size_t)(n - 1) * kb;
+      Ri[ol] = recip(p);
+      Ua[ol] = 0.0;
+      Ub[ol] = 0.0;
+      for (int it = 0; it < 3; ++it) {
+        double carry = X[0];
+#pragma unroll 4
+        for (int kk = 0; kk + 1 < n; ++kk) {
+          const size_t o = (size_t)kk * kb;
+          const double nx = X[o + kb];
+          const bool sw = Pv[o] != 0.0;
+          const double a = sw ? nx : carry;
+          carry = fma(-Lm[o], a, sw ? carry : nx);
+          X[o] = a;
+        }
+        X[ol] = carry;
+        double y1 = 0.0, y2 = 0.0, mx = 0.0;
+#pragma unroll 4
+        for (int kk = n - 1; kk >= 0; --kk) {
+          const size_t o = (size_t)kk * kb;
+          const double y = fma(-Ub[o], y2, fma(-Ua[o], y1, X[o])) * Ri[o];
+          X[o] = y;
+          mx = fmax(mx, fabs(y));
+          y2 = y1;
+          y1 = y;
+        }
+        // scaled by the largest entry first (no overflow in the squares); by a
+        // reciprocal unless the largest entry is so small that it overflows
+        const bool by_div = mx > 0.0 && mx < 0x1p-1000;
+        const double rm = (mx > 0.0 && !by_div) ? 1.0 / mx : 1.0;
+        double nr = 0.0;
+        for (int i = 0; i < n; ++i) {
+          const double x = X[(size_t)i * kb], y = by_div ? x / mx : x * rm;
+          nr = fma(y, y, nr);
+        }
+        const double rn = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0, sc = rm * rn;
+        for (int i = 0; i < n; ++i) {
+          const double x = X[(size_t)i * kb];
+          X[(size_t)i * kb] = by_div ? (x / mx) * rn : x * sc;
+        }
+      }
+      double *z = colq(c);
+      for (int i = 0; i < n; ++i) z[i] = X[(size_t)i * kb];
+    }
+    __syncthreads();  // the scratch is reused by the next batch
+  }
   int cs = 0;
   double lam_prev = 0.0;
   for (int c = 0; c < k; ++c) {
@@ -281,6 +367,7 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
       else if (gap <= sep) lam = lam_prev - sep;  // equal: shift apart
     }
     lam_prev = lam;
+    if (isolated(c)) continue;  // found above
     if (tid == 0) {
       // T - lam I = P L U (U with two superdiagonals): multipliers lm, 1/u1 in
       // ri, u2 in ua, u3 in ub, row swaps in pv
@@ -302,6 +389,8 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
       }
       p = (fabs(p) < tiny) ? ((p < 0.0) ? -tiny : tiny) : p;
       ri[n - 1] = recip(p);
+      ua[n - 1] = 0.0;  // (multiplied by zero in the back substitution)
+      ub[n - 1] = 0.0;
     }
     double xi = (tid < n) ? start_value(tid, c) : 0.0;
     for (int it = 0; it < 3; ++it) {
@@ -358,6 +447,8 @@ __global__ __launch_bounds__(256) void eig_vectors_kernel(const double *__restri
     __syncthreads();  // the vector is read by the next ones of its cluster
   }
   // back to A's basis: x = H_0 ... H_{n-3} z; wave wid takes vectors wid, wid + 4, ...
+  for (int idx = tid; idx < n * n; idx += blockDim.x) vh[idx] = work[idx];
+  __syncthreads();
   for (int c = wid; c < k; c += 4) {
     double *zc = colq(c);
     double z0 = lane < n ? zc[lane] : 0.0, z1 = lane + 64 < n ? zc[lane + 64] : 0.0;
@@ -382,7 +473,12 @@ size_t eig_work_elems(int n) { return (size_t)n * n + 3 * (size_t)n; }
 
 // dynamic LDS of the tridiagonalisation and of the vectors (the staged
 // reflections); each kernel adds at most 16 KiB of static LDS
-static size_t vectors_lds_bytes(int n) { return (size_t)n * n * sizeof(double); }
+// (the vectors' LDS also holds, before the reflections, six n-long arrays for
+// each of up to kb isolated vectors at a time: at least min(k, 16) of them)
+static size_t vectors_lds_elems(int n, int k) {
+  return std::max((size_t)n * n, 6 * (size_t)n * (size_t)std::min(k, 16));
+}
+static size_t vectors_lds_bytes(int n) { return vectors_lds_elems(n, 16) * sizeof(double); }
 
 bool eig_small_supported(int n) {
   if (n < 1 || n > kEigMaxN) return false;
@@ -427,12 +523,13 @@ hipError_t launch_eig_vectors(const double *work, int n, const double *w, int k,
                               int64_t ldq, int desc_cols, hipStream_t s) {
   if (n < 1 || n > kEigMaxN || k < 0 || k > n || ldq < n) return hipErrorInvalidValue;
   if (k == 0) return hipSuccess;
-  const size_t lds = vectors_lds_bytes(n);
+  const size_t elems = vectors_lds_elems(n, k), lds = elems * sizeof(double);
+  const int kb = (int)std::min((size_t)k, elems / (6 * (size_t)n));  // >= min(k, 16), <= 21
   hipError_t e = hipFuncSetAttribute((const void *)eig_vectors_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eig_vectors_kernel, dim3(1), dim3(256), lds, s, work, n, w, k, Q, ldq,
-                     desc_cols);
+                     desc_cols, kb);
   return hipGetLastError();
 }
 

@@ -5,8 +5,9 @@ indefinite matrices: every eigenvalue within a few u ||A||, the rank rule's
 decision from the GPU eigenvalues equal to the oracle's, the kept subspace
 (projector) within u ||A|| / gap, residuals and orthonormality of the vectors,
 and the degenerate cases (order 1 and 2, zero, diagonal and tridiagonal
-matrices, a multiple top eigenvalue, a graded spectrum, the upper triangle
-ignored, argument errors).
+matrices, a multiple top eigenvalue, a graded spectrum, many kept vectors with
+isolated and clustered eigenvalues, the upper triangle ignored, argument
+errors).
 """
 
 import numpy as np
@@ -142,6 +143,24 @@ def test_graded_spectrum_like_an_initial_gram():
         gap = min(lam[c - 1] - lam[c] if c > 0 else np.inf, lam[c] - lam[c + 1])
         assert 1.0 - abs(q[:, c] @ p[:, c]) <= (64 * n * U * lam[0] / gap) ** 2 + 1e-14
     _check_vectors(g, w, q, 64 * U * n)
+
+
+@pytest.mark.parametrize("n,k", [(128, 128), (100, 50), (64, 33)])
+def test_many_vectors_isolated_and_clustered(n, k):
+    """Many kept vectors at once: the isolated ones are found in parallel in
+    batches (several batches here), the clustered ones one by one with
+    orthogonalisation; all must be eigenvectors and orthonormal together."""
+    rng = np.random.default_rng(300 + n)
+    qq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.linspace(1.0, 2.0, n)
+    m = n // 2
+    d[m:m + 3] = d[m] + np.array([0.0, 1e-9, 2e-9])  # a tight cluster of three
+    d[5:7] = d[5]  # and a double eigenvalue
+    a = (qq * d) @ qq.T
+    a = 0.5 * (a + a.T)
+    w, q = _symeig(a, k)
+    np.testing.assert_allclose(w, np.sort(d), rtol=0, atol=16 * n * U * 2.0)
+    _check_vectors(a, w, q, 64 * U * n)
 
 
 def test_argument_errors():
