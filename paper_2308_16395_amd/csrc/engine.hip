@@ -551,7 +551,7 @@ struct st_handle {
   hipError_t init_g0(int64_t R, int rk);
   hipError_t chunk_gram(const double *X, int64_t R, int r, double *out);
   int qr_fix(const double *Gtop, int rdi, const double *vte, const double *ee, const double *pv,
-             int nxt);
+             double tol, int nxt);
   int do_reconstruct_slice(int64_t t, float *out);
   void destroy();
 };
@@ -1149,7 +1149,7 @@ int st_handle::do_update(const float *y, int64_t bsz) {
     e = qrg.ensure((size_t)rdi * rdi);
     if (e == hipSuccess) e = chunk_gram(V[cur].p, Rold, rdi, qrg.p);
     if (e != hipSuccess) return hipfail(e, "V^T V");
-    rc = qr_fix(qrg.p, rdi, vte, eev, pvec, nxt);
+    rc = qr_fix(qrg.p, rdi, vte, eev, pvec, tol, nxt);
     toc(ST_K_ORTH, 2.0 * Rold * rdi * rdi + 40.0 * (double)nn * nn * nn, 8.0 * Rold * rdi);
     if (rc != ST_OK) return rc;
     settle();
@@ -1461,7 +1461,7 @@ int st_handle::stream_factored(const RowMap &map, const double *dvec, int64_t Ro
       e = launch_small_gemm(1, M, rdi, qrg.p + (size_t)rdi * rdi, rdi, qrg.p, rdi, rdi, rdi, rdi,
                             stream);
     if (e != hipSuccess) return hipfail(e, "V^T V");
-    const int rc = qr_fix(qrg.p, rdi, qvte.p, ee, p.p, nxt);
+    const int rc = qr_fix(qrg.p, rdi, qvte.p, ee, p.p, tol, nxt);
     toc(ST_K_ORTH, 4.0 * (double)rdi * rdi * rdi + 40.0 * (double)nn * nn * nn,
         8.0 * 3.0 * rdi * rdi);
     if (rc != ST_OK) return rc;
@@ -1527,23 +1527,41 @@ hipError_t st_handle::chunk_gram(const double *X, int64_t R, int r, double *out)
 }
 
 // The QR fix of Alg. 3, taken when the orthogonality check on the new v fires:
-// [V v] = Q R and S' -> S' R^T, whose SVD is then taken densely (k_dense.hip).
-// Gtop = V^T V (r x r), vte = V^T e, ee = ||e||^2 (v = e / ||e||) and pv = p are
-// on the device. Writes U'' (U2), V'' = R^{-1} V_B (V2, so that V~ = [V v] V''
-// as without the fix) and S~ (S[nxt], descending); c = n = r + 1.
+// [V v] = Q R and S' -> S' R^T (k_dense.hip). Gtop = V^T V (r x r), vte = V^T e,
+// ee = ||e||^2 (v = e / ||e||) and pv = p are on the device; tol is the secular
+// solve's deflation tolerance. Writes U'' (U2), V'' (V2, so that V~ = [V v] V''
+// as without the fix) and S~ (S[nxt], descending); c = n = r + 1. The SVD of
+// S' R^T starts from the secular SVD of S' = U_S diag(S_S) V_S^T: S' R^T =
+// U_S A^T with A = R V_S diag(S_S), whose columns are orthogonal up to the
+// deviation the check measured, so the one-sided Jacobi on A (A J = U_A
+// diag(s')) ends in a sweep or two; U'' = U_S J and V'' = R^{-1} U_A =
+// V_S diag(S_S) J diag(s')^{-1}. Past kQrOrderMax columns the dense Jacobi SVD
+// of S' R^T and V'' = R^{-1} V_B by back substitution.
 int st_handle::qr_fix(const double *Gtop, int rdi, const double *vte, const double *ee,
-                      const double *pv, int nxt) {
+                      const double *pv, double tol, int nxt) {
   const int n = rdi + 1;
   const size_t nn2 = (size_t)n * n;
-  hipError_t e = qrw.ensure(3 * nn2 + n);
+  hipError_t e = qrw.ensure(7 * nn2 + 2 * (size_t)n);
   if (e == hipSuccess) e = qstat.ensure(2);
   if (e != hipSuccess) return hipfail(e, "QR fix buffers");
-  double *G = qrw.p, *A = G + nn2, *W = A + nn2, *sig = W + nn2;
+  double *G = qrw.p, *A = G + nn2, *W = A + nn2, *Us = W + nn2, *Vs = Us + nn2, *Jp = Vs + nn2,
+         *JpS = Jp + nn2, *Ss = JpS + nn2, *sig = Ss + n;
   e = launch_qr_gram_fill(Gtop, rdi, vte, ee, G, stream);
   if (e == hipSuccess) e = launch_chol_upper(G, n, qstat.p, stream);
-  if (e == hipSuccess) e = launch_arrow_rt(S[cur].p, pv, ee, G, rdi, A, stream);
-  if (e == hipSuccess) e = launch_jacobi_svd(A, n, W, 60, qstat.p, stream);
-  if (e == hipSuccess) e = launch_jacobi_finish(A, W, G, n, U2.p, V2.p, S[nxt].p, sig, stream);
+  if (n <= kQrOrderMax) {
+    if (e == hipSuccess)
+      e = launch_secular_svd(secdata(rdi), S[cur].p, pv, 0.0, ee, 1, tol, n, Us, Vs, Ss, stream);
+    if (e == hipSuccess) e = launch_form_rvs(G, n, Vs, n, Ss, A, stream);
+    if (e == hipSuccess) e = launch_jacobi_svd(A, n, W, 60, qstat.p, stream);
+    if (e == hipSuccess) e = launch_qr_order(A, W, n, Ss, S[nxt].p, Jp, JpS, stream);
+    if (e == hipSuccess) e = launch_small_gemm(0, Us, n, Jp, n, U2.p, n, n, n, n, stream);
+    if (e == hipSuccess) e = launch_small_gemm(0, Vs, n, JpS, n, V2.p, n, n, n, n, stream);
+  } else {
+    if (e == hipSuccess) e = launch_arrow_rt(S[cur].p, pv, ee, G, rdi, A, stream);
+    if (e == hipSuccess) e = launch_jacobi_svd(A, n, W, 60, qstat.p, stream);
+    if (e == hipSuccess)
+      e = launch_jacobi_finish(A, W, G, n, U2.p, V2.p, S[nxt].p, sig, stream);
+  }
   int st[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(st, qstat.p, sizeof(st), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
