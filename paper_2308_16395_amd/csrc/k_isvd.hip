@@ -1217,23 +1217,39 @@ hipError_t launch_g0_update(const double *G0, int r, const double *g, const doub
 
 // out[i] = sum_b part[b * n + i] (b < nb), one thread per entry, in a fixed
 // order: four interleaved partial sums, then their pairwise sum.
-__global__ void batch_sum_kernel(const double *part, int nb, int64_t n, double *out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  int b = 0;
-  for (; b + 4 <= nb; b += 4) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] += part[(size_t)(b + c) * n + i];
+// Blocks of 64 outputs and 16 waves: wave w sums the partials w, w + 16, ...
+// (rows of 64 consecutive doubles, two chains), then the 16 wave sums are
+// added in a fixed order. Spreading the partials over the waves keeps many
+// loads in flight even when there are few outputs (a small Gram over many
+// row chunks).
+__global__ __launch_bounds__(1024) void batch_sum_kernel(const double *part, int nb, int64_t n,
+                                                         double *out) {
+  __shared__ double ws[16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  double a0 = 0.0, a1 = 0.0;
+  if (i < n) {
+    int b = w;
+    for (; b + 16 < nb; b += 32) {
+      a0 += part[(size_t)b * n + i];
+      a1 += part[(size_t)(b + 16) * n + i];
+    }
+    if (b < nb) a0 += part[(size_t)b * n + i];
   }
-  for (int c = 0; b < nb; ++b, ++c) a[c] += part[(size_t)b * n + i];
-  out[i] = (a[0] + a[1]) + (a[2] + a[3]);
+  ws[w][lane] = a0 + a1;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += ws[q][lane];
+    out[i] = t;
+  }
 }
 
 hipError_t launch_batch_sum(const double *part, int nb, int64_t n, double *out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (nb < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(batch_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+  hipLaunchKernelGGL(batch_sum_kernel, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part,
                      nb, n, out);
   return hipGetLastError();
 }
