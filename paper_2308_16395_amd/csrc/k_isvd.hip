@@ -766,23 +766,30 @@ hipError_t launch_f32_to_f64(const float *x, int64_t n, double *y, hipStream_t s
 // the small orthogonal M (r x r) rotated (Sec. 3.2's auxiliary V kept as a
 // product; the core is C = V x_d S).
 // ---------------------------------------------------------------------------
-__global__ void small_gemv_kernel(const double *M, int n, const double *x, int trans, double *y,
-                                  const double *add, double *y2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// y = M x or M^T x (M n x n), and y2 = y + add when y2 is set: one wave per
+// output (its lanes stride the sum, then a DPP wave sum), four per block. y
+// must not overlap x.
+__global__ __launch_bounds__(256) void small_gemv_kernel(const double *M, int n, const double *x,
+                                                         int trans, double *y, const double *add,
+                                                         double *y2) {
+  const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;  // (uniform per wave)
   double acc = 0.0;
   if (trans)
-    for (int l = 0; l < n; ++l) acc += M[l + (size_t)n * i] * x[l];
+    for (int l = lane; l < n; l += 64) acc += M[l + (size_t)n * i] * x[l];
   else
-    for (int l = 0; l < n; ++l) acc += M[i + (size_t)n * l] * x[l];
-  y[i] = acc;
-  if (y2) y2[i] = acc + add[i];
+    for (int l = lane; l < n; l += 64) acc += M[i + (size_t)n * l] * x[l];
+  acc = dpp_wave_sum(acc);
+  if (lane == 0) {
+    y[i] = acc;
+    if (y2) y2[i] = acc + add[i];
+  }
 }
 
 hipError_t launch_small_gemv(const double *M, int n, const double *x, int trans, double *y,
                              const double *add, double *y2, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(small_gemv_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, M, n, x,
+  hipLaunchKernelGGL(small_gemv_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, M, n, x,
                      trans, y, add, y2);
   return hipGetLastError();
 }
