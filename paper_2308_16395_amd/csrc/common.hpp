@@ -70,6 +70,14 @@ __device__ inline double dpp_wave_sum(double v) {
   return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
+__device__ inline double dpp_wave_prod(double v) {
+  v *= dpp_move<0xB1>(v);
+  v *= dpp_move<0x4E>(v);
+  v *= dpp_move<0x141>(v);
+  v *= dpp_move<0x140>(v);
+  return (lane_value(v, 0) * lane_value(v, 16)) * (lane_value(v, 32) * lane_value(v, 48));
+}
+
 __device__ inline double dpp_wave_max(double v) {
   v = fmax(v, dpp_move<0xB1>(v));
   v = fmax(v, dpp_move<0x4E>(v));

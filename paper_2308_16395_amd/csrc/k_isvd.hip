@@ -326,17 +326,18 @@ hipError_t launch_colsum(const double *part, int nb, int r, double *out, const d
 // ---------------------------------------------------------------------------
 struct WaveRed {
   int lane;
+  // (the sums and products run with every lane of the wave active: DPP moves)
   template <class F>
   __device__ double sum(int m, F f) const {
     double acc = 0.0;
     for (int j = lane; j < m; j += kWave) acc += f(j);
-    return wave_sum(acc);
+    return dpp_wave_sum(acc);
   }
   template <class F>
   __device__ double prod(int m, F f) const {
     double acc = 1.0;
     for (int j = lane; j < m; j += kWave) acc *= f(j);
-    return wave_prod(acc);
+    return dpp_wave_prod(acc);
   }
   template <class F>
   __device__ void for_each(int m, F f) const {
